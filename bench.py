@@ -1,0 +1,165 @@
+"""Benchmark of the A-tSNE high-dimensional similarity path on one MI355X.
+
+A step is one pass of the whole path over the image-shaped workload
+(N = 70000 points, D = 784, perplexity 30, K = 90): exact kNN
+(atsne_knn, FP32 contraction) -> perplexity calibration (atsne_calibrate_p)
+-> symmetrisation (atsne_symmetrize), inputs resident in HBM.  The metric is
+points per second of the whole step.  The same line carries the BF16
+contraction + FP32 re-rank variant, the roofline of the dominant kernel
+(knn_tile, timed with HIP events on its own stream inside the timed
+region), per-stage times, and the FP64 CPU oracle timed on a bounded sample
+of the same workload on the host cores.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload imagelike|mixture]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+PEAK = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}  # dense MFMA TFLOP/s, MI355X
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="imagelike", choices=["imagelike", "mixture"])
+    ap.add_argument("--no-bf16", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_path(A, torch, Xt, mu, k, prec, steps, warmup):
+    """Warm up, then time `steps` whole-path steps; returns timing dict and last outputs."""
+    N, D = Xt.shape
+    ws = torch.empty(A.knn_workspace_size(N, N, D, k, prec), dtype=torch.uint8, device="cuda")
+    out = None
+    for _ in range(warmup):
+        idx, d2, fl = A.knn(Xt, k, prec=prec, workspace=ws)
+        P, beta, perp, fl = A.calibrate_p(d2, mu, flags=fl)
+        out = A.symmetrize(idx, P)
+    torch.cuda.synchronize()
+    A.profile_enable(True)
+    t0 = time.perf_counter()
+    for s in range(steps):
+        idx, d2, fl = A.knn(Xt, k, prec=prec, workspace=ws)
+        P, beta, perp, fl = A.calibrate_p(d2, mu, flags=fl)
+        rp, col, val = A.symmetrize(idx, P)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stages = {}
+    for name in ["knn_prep", "knn_tile", "knn_select", "knn_scan", "calibrate_rows", "sym_total"]:
+        ms, n = A.profile_read(name)
+        stages[name] = (ms, n)
+    A.profile_enable(False)
+    flags = fl.cpu().numpy()
+    return dict(wall=wall, stages=stages, idx=idx, P=P, val=val, flags=flags)
+
+
+def cpu_baseline(X, mu, k, target_s):
+    from oracle import oracle as O
+
+    o = O.get()
+    cores = o.max_threads()
+    rng = np.random.default_rng(12345)
+    probe = rng.choice(X.shape[0], size=64, replace=False).astype(np.int32)
+    t0 = time.perf_counter()
+    _, d2, _ = o.knn(X, k, query_ids=probe)
+    o.calibrate(d2, mu)
+    rate = 64 / (time.perf_counter() - t0)
+    m = int(min(X.shape[0], max(64, rate * target_s)))
+    rows = rng.choice(X.shape[0], size=m, replace=False).astype(np.int32)
+    t0 = time.perf_counter()
+    _, d2, _ = o.knn(X, k, query_ids=rows)
+    o.calibrate(d2, mu)
+    dt = time.perf_counter() - t0
+    return {"value": m / dt, "unit": "points/s", "cores": cores, "kind": "oracle",
+            "sample": "%d of %d query rows: FP64 exact kNN against the full corpus + bisection, %.1f s" % (
+                m, X.shape[0], dt)}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py: this build measures one GPU; --gpus %d is not supported (the path would shard by "
+              "query rows, see DESIGN.md)" % a.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_1512_01655_amd import atsne as A
+    from paper_1512_01655_amd import datagen
+
+    A.load()
+    if a.workload == "imagelike":
+        X = datagen.image_like()
+        name = "imagelike_N70000_D784_mu30_k90"
+    else:
+        X = datagen.mixture_isotropic()
+        name = "mixture10_N2000_D50_mu30_k90"
+    mu, k = 30.0, 90
+    N, D = X.shape
+    Xt = torch.from_numpy(X).cuda()
+    log("bench: %s on %s" % (name, torch.cuda.get_device_name(0)))
+
+    r = run_path(A, torch, Xt, mu, k, "fp32", a.steps, a.warmup)
+    ms_step = 1e3 * r["wall"] / a.steps
+    value = N * a.steps / r["wall"]
+    tile_ms, tile_n = r["stages"]["knn_tile"]
+    tile_avg_s = tile_ms / max(tile_n, 1) * 1e-3
+    # algorithmic work: 2*N*D FLOP per query point (full distance row), N
+    # queries per step, spread over tile_n / steps launches per step
+    flop_step = 2.0 * N * N * D
+    flop = flop_step * a.steps / max(tile_n, 1)  # per launch
+    achieved = flop / tile_avg_s / 1e12
+    stages_ms = {kname: round(v[0] / a.steps, 3) for kname, v in r["stages"].items()}
+    log("fp32: %.1f points/s, %.2f ms/step, stages %s" % (value, ms_step, stages_ms))
+    line = {
+        "metric": "kNN+P points/s at N=70k,D=784 (FP32 vs BF16+rerank)",
+        "value": round(value, 1), "unit": "points/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": name, "N": N, "D": D, "perplexity": mu, "k": k, "precision": "fp32",
+                   "k_cand": k + max(32, k // 2)},
+        "roofline": {"bound": "mfma", "kernel": "knn_tile", "achieved": round(achieved, 2),
+                     "peak": PEAK["fp32"], "unit": "TFLOP/s", "frac": round(achieved / PEAK["fp32"], 4),
+                     "traffic": None, "avg_launch_ms": round(tile_avg_s * 1e3, 3),
+                     "launches_per_step": tile_n / a.steps,
+                     "algorithmic": "2*N*D FLOP per query point x N queries per step, N=%d, D=%d" % (N, D)},
+        "stages_ms": stages_ms,
+        "rows_fp64_reranked": int((r["flags"] & 1).sum()), "rows_exact_scan": int(((r["flags"] & 8) > 0).sum()),
+    }
+    if not a.no_bf16:
+        rb = run_path(A, torch, Xt, mu, k, "bf16", a.steps, a.warmup)
+        vb = N * a.steps / rb["wall"]
+        tb_ms, tb_n = rb["stages"]["knn_tile"]
+        tb_avg = tb_ms / max(tb_n, 1) * 1e-3
+        ach_b = flop_step * a.steps / max(tb_n, 1) / tb_avg / 1e12
+        line["bf16_rerank"] = {
+            "value": round(vb, 1), "ms_per_step": round(1e3 * rb["wall"] / a.steps, 3),
+            "speedup_vs_fp32": round(vb / value, 3), "k_cand": 2 * k,
+            "stages_ms": {kname: round(v[0] / a.steps, 3) for kname, v in rb["stages"].items()},
+            "roofline": {"bound": "mfma", "kernel": "knn_tile", "achieved": round(ach_b, 2), "peak": PEAK["bf16"],
+                         "unit": "TFLOP/s", "frac": round(ach_b / PEAK["bf16"], 4)},
+            "agree_with_fp32_rows": float((rb["idx"] == r["idx"]).all(1).float().mean().item()),
+        }
+        log("bf16: %.1f points/s (x%.2f)" % (vb, vb / value))
+    if not a.no_cpu_baseline:
+        log("cpu baseline: timing the FP64 oracle on a bounded sample ...")
+        line["cpu_baseline"] = cpu_baseline(X, mu, k, a.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,255 @@
+/*
+ * atsne.h -- C ABI of the MI355X (gfx950) A-tSNE high-dimensional similarity
+ * library, libatsne.so.
+ *
+ * The library computes the exact sparse joint-probability matrix P that tSNE
+ * and its approximated variant A-tSNE start from (Pezzotti et al.,
+ * "Approximated and User Steerable tSNE for Progressive Visual Analytics",
+ * arXiv:1512.01655):
+ *   1. the K nearest neighbours of every point (Sec. 3.1, Eq. 8; squared
+ *      Euclidean distance of Eq. 3), K = floor(3 * perplexity);
+ *   2. per point, the Gaussian precision beta_i = 1/(2 sigma_i^2) that makes
+ *      the row's perplexity equal the target (Eq. 3, Eq. 4), and the
+ *      conditional probabilities p_{j|i} over the neighbour set;
+ *   3. the symmetric joint p_ij = (p_{j|i} + p_{i|j}) / (2N) (Eq. 2, Eq. 10).
+ * plus a serving loop for the paper's steerable, progressive use: point
+ * insertion (Sec. 5.3, Eq. 13) and per-point exact refinement of user
+ * selections (Sec. 4.3, Sec. 5.1).
+ *
+ * Conventions shared by every entry point
+ *   - Array arguments are DEVICE pointers owned by the caller unless stated
+ *     otherwise; the library never frees them.  Matrices are row-major.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Calls are
+ *     asynchronous on it unless documented to synchronise.
+ *   - `ws`/`ws_bytes`: scratch memory owned by the caller, at least the size
+ *     reported by the matching *_workspace_size query, 256-byte aligned.
+ *     ws == NULL asks the library to allocate (stream-ordered) and release it
+ *     inside the call.
+ *   - Return value: atsne_status.  On error nothing is launched, outputs are
+ *     untouched, and atsne_last_error() returns a message (thread-local).
+ *     No C++ exception crosses this boundary.
+ *   - Indices are int32 (N < 2^31); CSR row pointers are int64.
+ *   - Per-row outcome flags (uint8, device) use the ATSNE_FLAG_* bits.
+ */
+#ifndef ATSNE_H
+#define ATSNE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum atsne_status {
+    ATSNE_OK = 0,
+    ATSNE_E_INVALID_ARG = 1,   /* null pointer, bad size, bad stride, bad precision */
+    ATSNE_E_K_RANGE = 2,       /* k < 1, k > N-1, k_cand out of range, perplexity < 1 or >= k */
+    ATSNE_E_NOMEM = 3,         /* workspace too small, or an internal allocation failed */
+    ATSNE_E_HIP = 4,           /* a HIP runtime call or kernel launch failed */
+    ATSNE_E_NOT_CONVERGED = 5, /* strict calibration: some row did not converge */
+    ATSNE_E_BUSY = 6,          /* serving: request still pending / results unreleased */
+    ATSNE_E_UNSUPPORTED = 7    /* feature or precision not available on this device */
+} atsne_status;
+
+/* Arithmetic of the distance contraction (a2).  The neighbour distances
+ * returned are always FP32 direct differences of the FP32 source. */
+typedef enum atsne_precision {
+    ATSNE_PREC_FP32 = 0,     /* exact path: FP32 MFMA, certified candidate margin */
+    ATSNE_PREC_BF16 = 1,     /* BF16 (round-to-nearest-even) MFMA, FP32 accumulate */
+    ATSNE_PREC_FP8_E4M3 = 2  /* OCP FP8 e4m3 with per-row absmax scales, FP32 accumulate */
+} atsne_precision;
+
+/* Per-row flags. */
+#define ATSNE_FLAG_FP64_RERANKED 0x01u /* k-th/(k+1)-th gap below FP32 resolution: ranked in FP64 */
+#define ATSNE_FLAG_NOT_CONVERGED 0x02u /* bisection hit max_iter before reaching tol */
+#define ATSNE_FLAG_DEGENERATE 0x04u    /* target perplexity unreachable (equal or repeated distances) */
+#define ATSNE_FLAG_EXACT_SCAN 0x08u    /* FP32 path: candidate margin not certified; row redone by exact scan */
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char* atsne_last_error(void);
+/* Library version string. */
+const char* atsne_version(void);
+/* Device info for measurement: CU count and peak engine clock (kHz) of the current device. */
+atsne_status atsne_device_info(int32_t* n_cu, int32_t* clock_khz, int32_t* gcn_arch_major);
+
+/* Kernel timing for measurement (not needed for results).  When enabled,
+ * every kernel the library launches is bracketed by HIP events recorded on
+ * the stream it runs on; atsne_profile_read synchronises those events and
+ * returns, for kernels whose name starts with `name`, the summed elapsed
+ * time (ms) and the launch count.  Enabling clears earlier records. */
+atsne_status atsne_profile_enable(int32_t on);
+atsne_status atsne_profile_read(const char* name, double* total_ms, int64_t* count);
+
+/* ------------------------------------------------------------------ kNN -- */
+
+/* Scratch bytes needed by atsne_knn / atsne_knn_subset for a corpus of N rows
+ * of dimension D, M query rows, k neighbours and k_cand candidates
+ * (0 = the precision's default). */
+atsne_status atsne_knn_workspace_size(int64_t N, int64_t M, int32_t D, atsne_precision prec, int32_t k,
+                                      int32_t k_cand, size_t* bytes);
+
+/* Exact K nearest neighbours of every row of X among the other rows
+ * (Sec. 3.1, Eq. 8; squared Euclidean distance of Eq. 3).
+ *   X        [N x ld] FP32, row i = point x_i (first D columns used).
+ *   prec     arithmetic of the candidate search; see atsne_precision.
+ *   k        neighbours per row (the paper's K = floor(3 mu)), 1 <= k <= N-1.
+ *   k_cand   candidates re-ranked per row, k <= k_cand <= min(N-1, 1024);
+ *            0 selects the default (FP32: k + max(32, k/2); BF16/FP8: 2k).
+ *   nbr_idx  [N x k] int32 out: neighbour indices, ascending by (d, j).
+ *   nbr_d2   [N x k] FP32 out: squared distances, FP32 direct difference of
+ *            the FP32 rows (FP64 when ATSNE_FLAG_FP64_RERANKED).
+ *   flags    [N] uint8 out (may be NULL): ATSNE_FLAG_FP64_RERANKED,
+ *            ATSNE_FLAG_EXACT_SCAN.
+ * Self is excluded by index; exact duplicates are neighbours at distance 0;
+ * equal distances are ordered by the lower index.  Asynchronous. */
+atsne_status atsne_knn(const float* X, int64_t N, int32_t D, int64_t ld, atsne_precision prec, int32_t k,
+                       int32_t k_cand, int32_t* nbr_idx, float* nbr_d2, uint8_t* flags, void* ws,
+                       size_t ws_bytes, void* stream);
+
+/* As atsne_knn for the M query rows query_ids[0..M) (device int32, each in
+ * [0, N)) of the corpus X[0..N); each query excludes itself.  Outputs are
+ * [M x k] and [M].  This is the per-point exact refinement of Sec. 4.3
+ * applied to a selection (Sec. 5.1). */
+atsne_status atsne_knn_subset(const float* X, int64_t N, int32_t D, int64_t ld, const int32_t* query_ids,
+                              int64_t M, atsne_precision prec, int32_t k, int32_t k_cand, int32_t* nbr_idx,
+                              float* nbr_d2, uint8_t* flags, void* ws, size_t ws_bytes, void* stream);
+
+/* ----------------------------------------------------------- calibration -- */
+
+/* Perplexity calibration (Eq. 3, Eq. 4 restricted to the neighbour set of
+ * Eq. 8), one wavefront per row, bisection on beta in FP32.
+ *   nbr_d2     [N x k] FP32 squared neighbour distances (any order).
+ *   perplexity target mu, 1 <= mu < k.
+ *   tol        stop when |e^H - mu| <= tol (<= 0: default 1e-5); bisection
+ *              also stops when the bracket collapses to adjacent floats.
+ *   max_iter   bisection cap (<= 0: default 200).
+ *   strict     nonzero: synchronise the stream and return
+ *              ATSNE_E_NOT_CONVERGED if any row carries NOT_CONVERGED.
+ *   P_cond     [N x k] FP32 out: p_{j|i}, aligned with nbr_d2; rows sum to 1.
+ *   beta       [N] FP32 out: 1/(2 sigma_i^2) (+inf for a degenerate row whose
+ *              limit is beta -> inf; 0 when all distances are equal).
+ *   perp       [N] FP32 out (may be NULL): achieved perplexity e^H of the row.
+ *   flags      [N] uint8 in/out (may be NULL): NOT_CONVERGED and DEGENERATE
+ *              are OR-ed into the existing bits.
+ * Rows whose minimum-distance multiplicity m satisfies m >= mu cannot reach
+ * mu: they get the beta -> inf limit (uniform over the m) and DEGENERATE. */
+atsne_status atsne_calibrate_p(const float* nbr_d2, int64_t N, int32_t k, float perplexity, float tol,
+                               int32_t max_iter, int32_t strict, float* P_cond, float* beta, float* perp,
+                               uint8_t* flags, void* stream);
+
+/* -------------------------------------------------------- symmetrisation -- */
+
+/* Scratch bytes for atsne_symmetrize / atsne_symmetrize_csr with N rows and
+ * at most nnz_in conditional entries (N*k for the fixed-k form). */
+atsne_status atsne_symmetrize_workspace_size(int64_t N, int64_t nnz_in, size_t* bytes);
+
+/* Symmetric joint P of Eq. 2 (equivalently the split form of Eq. 10):
+ * p_ij = (p_{j|i} + p_{i|j}) / (2N) on the union of the neighbour patterns.
+ *   nbr_idx, P_cond  [N x k] neighbour indices and p_{j|i} (from atsne_knn
+ *                    and atsne_calibrate_p); indices in [0, N), no self.
+ *   row_ptr  [N+1] int64 out; col [2*N*k] int32 out; val [2*N*k] FP32 out
+ *            (capacity 2*N*k; the first *nnz_host entries are written).
+ *            Columns ascending within a row, no diagonal entries.
+ *   nnz_host HOST int64 out: number of stored entries, N*k <= nnz <= 2*N*k.
+ * Synchronises the stream once (to read nnz). */
+atsne_status atsne_symmetrize(const int32_t* nbr_idx, const float* P_cond, int64_t N, int32_t k,
+                              int64_t* row_ptr, int32_t* col, float* val, int64_t* nnz_host, void* ws,
+                              size_t ws_bytes, void* stream);
+
+/* As atsne_symmetrize for conditional rows of varying length given as CSR:
+ * in_ptr [N+1] int64, in_col/in_val [in_ptr[N]] (device).  Output capacity
+ * 2*in_ptr[N]; nnz_in_host is in_ptr[N] (host copy, so no extra sync). */
+atsne_status atsne_symmetrize_csr(const int64_t* in_ptr, const int32_t* in_col, const float* in_val,
+                                  int64_t N, int64_t nnz_in_host, int64_t* row_ptr, int32_t* col, float* val,
+                                  int64_t* nnz_host, void* ws, size_t ws_bytes, void* stream);
+
+/* --------------------------------------------------------------- serving -- */
+/* A server owns a device-resident corpus and its exact similarity state
+ * (neighbour lists, conditional rows, beta) and processes requests with
+ * continuous batching: requests that arrive while others run are admitted as
+ * slots and HBM budget free up, and their row tiles share the same batched
+ * kernel launches.  Two request kinds follow the paper's steerable use:
+ *   insert  (Sec. 5.3, Eq. 13): B new points join the corpus; their exact
+ *           neighbours are computed against the corpus (and each other), and
+ *           every resident row i takes a new point a when ||x_a - x_i|| is
+ *           below its current farthest neighbour d_i^Max, evicting it.
+ *   refine  (Sec. 4.3, Sec. 5.1): the exact neighbourhood and P row of a
+ *           user selection of M resident points is recomputed at a requested
+ *           perplexity (K_i = floor(3 mu_i) per row).
+ * Requests carry an epoch: a request sees exactly the corpus committed
+ * before it (inserts commit in arrival order), so its result does not depend
+ * on what else shares the GPU. */
+
+typedef struct atsne_server atsne_server;
+
+typedef struct atsne_serve_config {
+    size_t hbm_budget_bytes; /* cap on request scratch in flight (0 = 4 GiB) */
+    int32_t max_slots;       /* max requests in flight at once (0 = 8) */
+    int64_t capacity_rows;   /* corpus rows the server can grow to (0 = 2 * N) */
+    int32_t max_batch_rows;  /* rows per batched launch (0 = 16384) */
+    int32_t device;          /* HIP device ordinal (-1 = current) */
+} atsne_serve_config;
+
+typedef struct atsne_result {
+    uint64_t req_id;
+    int32_t kind;            /* 0 insert, 1 refine */
+    int32_t status;          /* atsne_status of the request */
+    uint64_t epoch;          /* corpus version the request ran against */
+    int64_t n_rows;          /* rows in the result (B or M) */
+    int32_t k;               /* neighbours per row */
+    float perplexity;
+    const int32_t* row_ids;  /* device [n_rows]: corpus ids of the result rows */
+    const int32_t* nbr_idx;  /* device [n_rows x k] */
+    const float* nbr_d2;     /* device [n_rows x k] */
+    const float* P_cond;     /* device [n_rows x k] */
+    const float* beta;       /* device [n_rows] */
+    const uint8_t* flags;    /* device [n_rows] */
+    int64_t n_changed;       /* insert: resident rows whose list changed (Eq. 13) */
+    const int32_t* changed;  /* device [n_changed] corpus ids (insert only) */
+    double t_submit_ms, t_admit_ms, t_complete_ms; /* host clock, ms since server start */
+} atsne_result;
+
+typedef struct atsne_serve_stats {
+    uint64_t submitted, completed, released;
+    uint64_t launches;        /* batched kNN launches issued */
+    uint64_t rows_processed;
+    int64_t corpus_rows;
+    size_t bytes_in_flight;
+    size_t peak_bytes_in_flight;
+    int32_t max_concurrent;   /* most requests seen in flight together */
+} atsne_serve_stats;
+
+/* Create a server over a copy of corpus [N x D] (device or host FP32, row
+ * stride D), with its exact kNN at perplexity mu (k = floor(3 mu)) computed
+ * at creation.  *out receives the handle. */
+atsne_status atsne_serve_create(const atsne_serve_config* cfg, const float* corpus, int64_t N, int32_t D,
+                                float perplexity, atsne_server** out);
+/* Queue an insert of B points X_new [B x D] (device FP32).  Returns at once
+ * with *req_id; the data is copied before return. */
+atsne_status atsne_serve_submit_insert(atsne_server* s, const float* X_new, int32_t B, uint64_t* req_id);
+/* Queue a refine of M corpus ids (host int32 array) at perplexity mu. */
+atsne_status atsne_serve_submit_refine(atsne_server* s, const int32_t* ids_host, int32_t M, float perplexity,
+                                       uint64_t* req_id);
+/* Non-blocking: ATSNE_E_BUSY while pending, else fills *out. */
+atsne_status atsne_serve_poll(atsne_server* s, uint64_t req_id, atsne_result* out);
+/* Blocking wait for completion, then fills *out. */
+atsne_status atsne_serve_wait(atsne_server* s, uint64_t req_id, atsne_result* out);
+/* Free a completed request's result buffers (server-owned until then). */
+atsne_status atsne_serve_release(atsne_server* s, uint64_t req_id);
+atsne_status atsne_serve_stats_get(atsne_server* s, atsne_serve_stats* out);
+/* Snapshot of the server's state at the latest committed epoch: copies the
+ * corpus rows and fixed-k lists (rows refined at another k are reported with
+ * their own k via k_rows) into caller device buffers of capacity cap_rows.
+ * Synchronises. */
+atsne_status atsne_serve_snapshot(atsne_server* s, int64_t cap_rows, float* corpus, int32_t* nbr_idx,
+                                  float* nbr_d2, int64_t* n_rows, uint64_t* epoch);
+/* Destroy: waits for in-flight work; ATSNE_E_BUSY if results are unreleased
+ * and force == 0. */
+atsne_status atsne_serve_destroy(atsne_server* s, int32_t force);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ATSNE_H */

@@ -1,0 +1,247 @@
+"""Thin ctypes binding over libatsne.so (C ABI in include/atsne.h).
+
+Argument marshalling only: every step of the similarity path runs in the HIP
+library.  Tensors are torch CUDA (HIP) tensors used as device buffers; the
+stream is torch's current stream unless one is given.  The binding raises
+if the library is missing -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from pathlib import Path
+
+import torch
+
+_HERE = Path(__file__).resolve().parent
+LIBPATH = _HERE / "libatsne.so"
+
+OK, E_INVALID_ARG, E_K_RANGE, E_NOMEM, E_HIP, E_NOT_CONVERGED, E_BUSY, E_UNSUPPORTED = range(8)
+PREC = {"fp32": 0, "bf16": 1, "fp8": 2, "fp8_e4m3": 2}
+FLAG_FP64_RERANKED, FLAG_NOT_CONVERGED, FLAG_DEGENERATE, FLAG_EXACT_SCAN = 1, 2, 4, 8
+
+# symbols declared by include/atsne.h
+EXPORTS = [
+    "atsne_last_error", "atsne_version", "atsne_device_info", "atsne_profile_enable", "atsne_profile_read",
+    "atsne_knn_workspace_size", "atsne_knn", "atsne_knn_subset",
+    "atsne_calibrate_p",
+    "atsne_symmetrize_workspace_size", "atsne_symmetrize", "atsne_symmetrize_csr",
+    "atsne_serve_create", "atsne_serve_submit_insert", "atsne_serve_submit_refine", "atsne_serve_poll",
+    "atsne_serve_wait", "atsne_serve_release", "atsne_serve_stats_get", "atsne_serve_snapshot",
+    "atsne_serve_destroy",
+]
+
+
+class AtsneError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("atsne status %d: %s" % (status, msg))
+        self.status = status
+
+
+_lib = None
+
+_p = ctypes.c_void_p
+_i32, _i64, _f32, _sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_size_t
+
+
+class ServeConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int32),
+                ("capacity_rows", ctypes.c_int64), ("max_batch_rows", ctypes.c_int32),
+                ("device", ctypes.c_int32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("req_id", ctypes.c_uint64), ("kind", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("epoch", ctypes.c_uint64), ("n_rows", ctypes.c_int64), ("k", ctypes.c_int32),
+                ("perplexity", ctypes.c_float), ("row_ids", _p), ("nbr_idx", _p), ("nbr_d2", _p),
+                ("P_cond", _p), ("beta", _p), ("flags", _p), ("n_changed", ctypes.c_int64), ("changed", _p),
+                ("t_submit_ms", ctypes.c_double), ("t_admit_ms", ctypes.c_double),
+                ("t_complete_ms", ctypes.c_double)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("released", ctypes.c_uint64),
+                ("launches", ctypes.c_uint64), ("rows_processed", ctypes.c_uint64), ("corpus_rows", ctypes.c_int64),
+                ("bytes_in_flight", ctypes.c_size_t), ("peak_bytes_in_flight", ctypes.c_size_t),
+                ("max_concurrent", ctypes.c_int32)]
+
+
+def load(path: Path | None = None) -> ctypes.CDLL:
+    """Load libatsne.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    path = Path(path) if path is not None else LIBPATH
+    if not path.exists():
+        raise RuntimeError("libatsne.so not built at %s: run python -m paper_1512_01655_amd.build" % path)
+    L = ctypes.CDLL(str(path))
+    L.atsne_last_error.restype = ctypes.c_char_p
+    L.atsne_version.restype = ctypes.c_char_p
+    sig = {
+        "atsne_device_info": [_p, _p, _p],
+        "atsne_profile_enable": [_i32],
+        "atsne_profile_read": [ctypes.c_char_p, _p, _p],
+        "atsne_knn_workspace_size": [_i64, _i64, _i32, ctypes.c_int, _i32, _i32, _p],
+        "atsne_knn": [_p, _i64, _i32, _i64, ctypes.c_int, _i32, _i32, _p, _p, _p, _p, _sz, _p],
+        "atsne_knn_subset": [_p, _i64, _i32, _i64, _p, _i64, ctypes.c_int, _i32, _i32, _p, _p, _p, _p, _sz, _p],
+        "atsne_calibrate_p": [_p, _i64, _i32, _f32, _f32, _i32, _i32, _p, _p, _p, _p, _p],
+        "atsne_symmetrize_workspace_size": [_i64, _i64, _p],
+        "atsne_symmetrize": [_p, _p, _i64, _i32, _p, _p, _p, _p, _p, _sz, _p],
+        "atsne_symmetrize_csr": [_p, _p, _p, _i64, _i64, _p, _p, _p, _p, _p, _sz, _p],
+        "atsne_serve_create": [_p, _p, _i64, _i32, _f32, _p],
+        "atsne_serve_submit_insert": [_p, _p, _i32, _p],
+        "atsne_serve_submit_refine": [_p, _p, _i32, _f32, _p],
+        "atsne_serve_poll": [_p, ctypes.c_uint64, _p],
+        "atsne_serve_wait": [_p, ctypes.c_uint64, _p],
+        "atsne_serve_release": [_p, ctypes.c_uint64],
+        "atsne_serve_stats_get": [_p, _p],
+        "atsne_serve_snapshot": [_p, _i64, _p, _p, _p, _p, _p],
+        "atsne_serve_destroy": [_p, _i32],
+    }
+    for name, args in sig.items():
+        try:
+            f = getattr(L, name)
+        except AttributeError:
+            continue  # the export test enforces the full symbol list
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    if path == LIBPATH:
+        _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != OK:
+        raise AtsneError(status, load().atsne_last_error().decode())
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev(X: torch.Tensor, dtype, name):
+    if not (X.is_cuda and X.dtype == dtype):
+        raise ValueError("%s must be a %s device tensor" % (name, dtype))
+
+
+def knn(X: torch.Tensor, k: int, prec: str = "fp32", k_cand: int = 0, query_ids: torch.Tensor | None = None,
+        stream=None, workspace: torch.Tensor | None = None):
+    """Exact kNN (atsne_knn / atsne_knn_subset).  Returns (nbr_idx int32, nbr_d2 float32, flags uint8)."""
+    L = load()
+    _dev(X, torch.float32, "X")
+    if X.dim() != 2 or X.stride(1) != 1:
+        raise ValueError("X must be 2-D with unit column stride")
+    N, D = X.shape
+    ld = X.stride(0)
+    M = N if query_ids is None else query_ids.numel()
+    if query_ids is not None:
+        _dev(query_ids, torch.int32, "query_ids")
+    need = ctypes.c_size_t()
+    _check(L.atsne_knn_workspace_size(N, M, D, PREC[prec], k, k_cand, ctypes.byref(need)))
+    if workspace is None or workspace.numel() < need.value:
+        workspace = torch.empty(max(1, need.value), dtype=torch.uint8, device=X.device)
+    idx = torch.empty((M, k), dtype=torch.int32, device=X.device)
+    d2 = torch.empty((M, k), dtype=torch.float32, device=X.device)
+    flags = torch.zeros((M,), dtype=torch.uint8, device=X.device)
+    if query_ids is None:
+        _check(L.atsne_knn(_ptr(X), N, D, ld, PREC[prec], k, k_cand, _ptr(idx), _ptr(d2), _ptr(flags),
+                           _ptr(workspace), workspace.numel(), _stream(stream)))
+    else:
+        _check(L.atsne_knn_subset(_ptr(X), N, D, ld, _ptr(query_ids), M, PREC[prec], k, k_cand, _ptr(idx),
+                                  _ptr(d2), _ptr(flags), _ptr(workspace), workspace.numel(), _stream(stream)))
+    return idx, d2, flags
+
+
+def knn_workspace_size(N: int, M: int, D: int, k: int, prec: str = "fp32", k_cand: int = 0) -> int:
+    need = ctypes.c_size_t()
+    _check(load().atsne_knn_workspace_size(N, M, D, PREC[prec], k, k_cand, ctypes.byref(need)))
+    return need.value
+
+
+def calibrate_p(nbr_d2: torch.Tensor, perplexity: float, tol: float = 0.0, max_iter: int = 0, strict: bool = False,
+                flags: torch.Tensor | None = None, stream=None):
+    """Perplexity bisection (atsne_calibrate_p).  Returns (P_cond, beta, perp, flags)."""
+    L = load()
+    _dev(nbr_d2, torch.float32, "nbr_d2")
+    nbr_d2 = nbr_d2.contiguous()
+    N, k = nbr_d2.shape
+    P = torch.empty_like(nbr_d2)
+    beta = torch.empty((N,), dtype=torch.float32, device=nbr_d2.device)
+    perp = torch.empty((N,), dtype=torch.float32, device=nbr_d2.device)
+    if flags is None:
+        flags = torch.zeros((N,), dtype=torch.uint8, device=nbr_d2.device)
+    _check(L.atsne_calibrate_p(_ptr(nbr_d2), N, k, float(perplexity), float(tol), int(max_iter), int(strict),
+                               _ptr(P), _ptr(beta), _ptr(perp), _ptr(flags), _stream(stream)))
+    return P, beta, perp, flags
+
+
+def symmetrize(nbr_idx: torch.Tensor, P_cond: torch.Tensor, stream=None, workspace: torch.Tensor | None = None):
+    """Symmetric joint P as CSR (atsne_symmetrize).  Returns (row_ptr int64, col int32, val float32)."""
+    L = load()
+    _dev(nbr_idx, torch.int32, "nbr_idx")
+    _dev(P_cond, torch.float32, "P_cond")
+    nbr_idx, P_cond = nbr_idx.contiguous(), P_cond.contiguous()
+    N, k = nbr_idx.shape
+    need = ctypes.c_size_t()
+    _check(L.atsne_symmetrize_workspace_size(N, N * k, ctypes.byref(need)))
+    if workspace is None or workspace.numel() < need.value:
+        workspace = torch.empty(max(1, need.value), dtype=torch.uint8, device=nbr_idx.device)
+    row_ptr = torch.empty((N + 1,), dtype=torch.int64, device=nbr_idx.device)
+    col = torch.empty((2 * N * k,), dtype=torch.int32, device=nbr_idx.device)
+    val = torch.empty((2 * N * k,), dtype=torch.float32, device=nbr_idx.device)
+    nnz = ctypes.c_int64()
+    _check(L.atsne_symmetrize(_ptr(nbr_idx), _ptr(P_cond), N, k, _ptr(row_ptr), _ptr(col), _ptr(val),
+                              ctypes.byref(nnz), _ptr(workspace), workspace.numel(), _stream(stream)))
+    return row_ptr, col[:nnz.value], val[:nnz.value]
+
+
+def symmetrize_csr(in_ptr: torch.Tensor, in_col: torch.Tensor, in_val: torch.Tensor, stream=None):
+    """Symmetrise variable-length conditional rows given as CSR (atsne_symmetrize_csr)."""
+    L = load()
+    N = in_ptr.numel() - 1
+    nnz_in = int(in_ptr[-1].item())
+    need = ctypes.c_size_t()
+    _check(L.atsne_symmetrize_workspace_size(N, nnz_in, ctypes.byref(need)))
+    ws = torch.empty(max(1, need.value), dtype=torch.uint8, device=in_ptr.device)
+    row_ptr = torch.empty((N + 1,), dtype=torch.int64, device=in_ptr.device)
+    col = torch.empty((max(1, 2 * nnz_in),), dtype=torch.int32, device=in_ptr.device)
+    val = torch.empty((max(1, 2 * nnz_in),), dtype=torch.float32, device=in_ptr.device)
+    nnz = ctypes.c_int64()
+    _check(L.atsne_symmetrize_csr(_ptr(in_ptr), _ptr(in_col), _ptr(in_val), N, nnz_in, _ptr(row_ptr), _ptr(col),
+                                  _ptr(val), ctypes.byref(nnz), _ptr(ws), ws.numel(), _stream(stream)))
+    return row_ptr, col[:nnz.value], val[:nnz.value]
+
+
+def similarity(X: torch.Tensor, perplexity: float, prec: str = "fp32", k: int | None = None, k_cand: int = 0,
+               stream=None):
+    """kNN -> calibration -> symmetrisation, K = floor(3 mu) unless k is given."""
+    if k is None:
+        k = int(math.floor(3.0 * perplexity))
+    idx, d2, flags = knn(X, k, prec=prec, k_cand=k_cand, stream=stream)
+    P, beta, perp, flags = calibrate_p(d2, perplexity, flags=flags, stream=stream)
+    row_ptr, col, val = symmetrize(idx, P, stream=stream)
+    return dict(idx=idx, d2=d2, flags=flags, P=P, beta=beta, perp=perp, row_ptr=row_ptr, col=col, val=val)
+
+
+def device_info():
+    n_cu, clk, major = _i32(), _i32(), _i32()
+    _check(load().atsne_device_info(ctypes.byref(n_cu), ctypes.byref(clk), ctypes.byref(major)))
+    return dict(n_cu=n_cu.value, clock_khz=clk.value, arch_major=major.value)
+
+
+def profile_enable(on: bool = True):
+    """Start (clearing earlier records) or stop per-kernel HIP-event timing."""
+    _check(load().atsne_profile_enable(1 if on else 0))
+
+
+def profile_read(name: str):
+    """(total_ms, launches) of library kernels whose name starts with `name`."""
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    _check(load().atsne_profile_read(name.encode(), ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value

@@ -1,0 +1,134 @@
+"""GPU kNN (atsne_knn / atsne_knn_subset) against the FP64 oracle."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1512_01655_amd import datagen
+from tests import parity
+from tests.gpu_common import lib, run_knn, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def A():
+    return lib()
+
+
+@pytest.fixture(scope="module")
+def ora():
+    return O.get()
+
+
+def _compare(A, ora, X, k, prec="fp32", kc=0, qids=None, exact=False):
+    g_idx, g_d2, g_fl = run_knn(A, X, k, prec, kc, qids)
+    o_idx, o_d2, o_nx = ora.knn(X, k, query_ids=qids)
+    rows = np.arange(X.shape[0]) if qids is None else np.asarray(qids)
+    if exact:
+        assert np.array_equal(g_idx, o_idx)
+        assert np.array_equal(g_d2.astype(np.float64), o_d2)
+        return g_fl
+    ties, _ = parity.check_knn(X, rows, g_idx, g_d2, o_idx, o_d2, o_nx)
+    say("    tie-rule rows %d / %d, fp64-reranked %d, exact-scan %d" % (
+        ties, len(rows), int((g_fl & 1).sum()), int((g_fl & 8).sum() // 8)))
+    return g_fl
+
+
+@pytest.mark.parametrize("case", range(7))
+def test_knn_small_ragged(A, ora, case):
+    X = datagen.small_cases()[case]
+    N = X.shape[0]
+    for k in sorted({1, 7, min(90, N - 1), N - 1}):
+        _compare(A, ora, X, k)
+
+
+def test_knn_config1_full(A, ora):
+    X = datagen.mixture_isotropic()
+    _compare(A, ora, X, 90)
+
+
+def test_knn_config1_kcand_equals_k(A, ora):
+    # no candidate margin: the certificate must route uncertain rows to the exact scan
+    X = datagen.mixture_isotropic()
+    _compare(A, ora, X, 90, kc=90)
+
+
+def test_knn_integer_ties_exact(A, ora):
+    # small integers: every distance is exact in FP32, so the (d, j) ranking,
+    # ties included, must match bit for bit
+    rng = np.random.default_rng(3)
+    for N, D, k in [(300, 4, 20), (1000, 3, 50), (600, 40, 90)]:
+        X = rng.integers(-3, 4, size=(N, D)).astype(np.float32)
+        _compare(A, ora, X, k, exact=True)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+def test_knn_representable_exact_all_precisions(A, ora, prec):
+    # integers in [-7, 7] with a 7 in every row are exact in FP32, BF16 and
+    # (scale 7/448 = 2^-6) FP8 e4m3, so all three contractions are exact
+    rng = np.random.default_rng(4)
+    for N, D, k in [(700, 50, 30), (1300, 128, 90), (520, 200, 10)]:
+        X = rng.integers(-7, 8, size=(N, D)).astype(np.float32)
+        X[:, 0] = 7.0
+        _compare(A, ora, X, k, prec=prec, exact=True)
+
+
+def test_knn_duplicates(A, ora):
+    rng = np.random.default_rng(5)
+    base = rng.normal(size=(300, 16)).astype(np.float32)
+    X = np.concatenate([base, base, base])[rng.permutation(900)]
+    _compare(A, ora, X, 10, exact=False)
+    g_idx, g_d2, _ = run_knn(A, X, 10)
+    o_idx, o_d2, _ = ora.knn(X, 10)
+    assert np.array_equal(g_idx[:, :2], o_idx[:, :2])  # the two exact copies, lower index first
+    assert np.all(g_d2[:, :2] == 0)
+
+
+def test_knn_all_equal(A, ora):
+    X = np.ones((600, 33), np.float32)
+    g_idx, g_d2, g_fl = run_knn(A, X, 25)
+    for i in range(600):
+        exp = [j for j in range(27) if j != i][:25]
+        assert g_idx[i].tolist() == exp
+    assert np.all(g_d2 == 0)
+
+
+def test_knn_subset(A, ora):
+    X = datagen.mixture_isotropic()
+    q = np.random.default_rng(6).choice(2000, size=333, replace=False).astype(np.int32)
+    _compare(A, ora, X, 90, qids=q)
+
+
+def test_knn_errors(A):
+    import torch
+
+    X = torch.zeros((10, 4), device="cuda")
+    with pytest.raises(A.AtsneError) as e:
+        A.knn(X, 10)
+    assert e.value.status == A.E_K_RANGE
+    with pytest.raises(A.AtsneError) as e:
+        A.knn(X, 3, k_cand=2)
+    assert e.value.status == A.E_K_RANGE
+
+
+def test_knn_config2_sampled(A, ora):
+    # full 70000 x 784 run at the benchmark's launch configuration; the oracle
+    # checks a seeded sample of rows one by one
+    X = datagen.image_like()
+    g_idx, g_d2, g_fl = run_knn(A, X, 90)
+    rows = np.random.default_rng(7).choice(X.shape[0], size=200, replace=False).astype(np.int32)
+    o_idx, o_d2, o_nx = ora.knn(X, 90, query_ids=rows)
+    ties, _ = parity.check_knn(X, rows, g_idx[rows], g_d2[rows], o_idx, o_d2, o_nx)
+    say("    config2 sample: tie-rule rows %d/200; fp64 rows %d, exact-scan rows %d (of 70000)" % (
+        ties, int((g_fl & 1).sum()), int(((g_fl & 8) > 0).sum())))
+    assert np.all(np.diff(g_d2, axis=1) >= 0)
+
+
+def test_knn_bf16_recall_config2(A, ora):
+    X = datagen.image_like()
+    g_idx, g_d2, g_fl = run_knn(A, X, 90, prec="bf16")
+    rows = np.random.default_rng(8).choice(X.shape[0], size=200, replace=False).astype(np.int32)
+    o_idx, o_d2, o_nx = ora.knn(X, 90, query_ids=rows)
+    rec = O.recall(g_idx[rows], o_idx)
+    say("    bf16 recall on 200 rows: %.5f" % rec)
+    assert rec >= 0.999
