@@ -217,7 +217,8 @@ typedef struct atsne_serve_stats {
     int64_t corpus_rows;
     size_t bytes_in_flight;
     size_t peak_bytes_in_flight;
-    int32_t max_concurrent;   /* most requests seen in flight together */
+    int32_t max_concurrent;   /* most requests admitted (in flight) at once */
+    int32_t max_requests_per_launch; /* most distinct requests sharing one batched launch */
 } atsne_serve_stats;
 
 /* Create a server over a copy of corpus [N x D] (device or host FP32, row

@@ -63,7 +63,7 @@ class ServeStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("released", ctypes.c_uint64),
                 ("launches", ctypes.c_uint64), ("rows_processed", ctypes.c_uint64), ("corpus_rows", ctypes.c_int64),
                 ("bytes_in_flight", ctypes.c_size_t), ("peak_bytes_in_flight", ctypes.c_size_t),
-                ("max_concurrent", ctypes.c_int32)]
+                ("max_concurrent", ctypes.c_int32), ("max_requests_per_launch", ctypes.c_int32)]
 
 
 def load(path: Path | None = None) -> ctypes.CDLL:
@@ -99,10 +99,7 @@ def load(path: Path | None = None) -> ctypes.CDLL:
         "atsne_serve_destroy": [_p, _i32],
     }
     for name, args in sig.items():
-        try:
-            f = getattr(L, name)
-        except AttributeError:
-            continue  # the export test enforces the full symbol list
+        f = getattr(L, name)
         f.argtypes = args
         f.restype = ctypes.c_int
     if path == LIBPATH:
@@ -245,3 +242,129 @@ def profile_read(name: str):
     ms, n = ctypes.c_double(), ctypes.c_int64()
     _check(load().atsne_profile_read(name.encode(), ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+# --------------------------------------------------------------------------- serving
+_hip = None
+
+
+def _hip_lib():
+    global _hip
+    if _hip is None:
+        _hip = ctypes.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.argtypes = [_p, _p, ctypes.c_size_t, ctypes.c_int]
+        _hip.hipMemcpy.restype = ctypes.c_int
+    return _hip
+
+
+def _d2h(ptr, shape, dtype):
+    import numpy as np
+
+    out = np.empty(shape, dtype=dtype)
+    if out.size:
+        rc = _hip_lib().hipMemcpy(out.ctypes.data_as(_p), ctypes.c_void_p(ptr), out.nbytes, 2)  # DeviceToHost
+        if rc != 0:
+            raise RuntimeError("hipMemcpy D2H failed (%d)" % rc)
+    return out
+
+
+class Server:
+    """Continuous-batching server over a device-resident corpus (atsne_serve_*)."""
+
+    def __init__(self, corpus: torch.Tensor, perplexity: float, hbm_budget_bytes: int = 0, max_slots: int = 0,
+                 capacity_rows: int = 0, max_batch_rows: int = 0):
+        L = load()
+        _dev(corpus, torch.float32, "corpus")
+        corpus = corpus.contiguous()
+        self.N0, self.D = corpus.shape
+        cfg = ServeConfig(hbm_budget_bytes, max_slots, capacity_rows, max_batch_rows, -1)
+        h = ctypes.c_void_p()
+        torch.cuda.synchronize()
+        _check(L.atsne_serve_create(ctypes.byref(cfg), _ptr(corpus), self.N0, self.D, float(perplexity),
+                                    ctypes.byref(h)))
+        self.h = h
+        self.perplexity = perplexity
+
+    def insert(self, X_new: torch.Tensor) -> int:
+        _dev(X_new, torch.float32, "X_new")
+        X_new = X_new.contiguous()
+        torch.cuda.synchronize()
+        rid = ctypes.c_uint64()
+        _check(load().atsne_serve_submit_insert(self.h, _ptr(X_new), X_new.shape[0], ctypes.byref(rid)))
+        return rid.value
+
+    def refine(self, ids, perplexity: float) -> int:
+        import numpy as np
+
+        ids = np.ascontiguousarray(ids, dtype=np.int32)
+        rid = ctypes.c_uint64()
+        _check(load().atsne_serve_submit_refine(self.h, ids.ctypes.data_as(_p), ids.size, float(perplexity),
+                                                ctypes.byref(rid)))
+        return rid.value
+
+    @staticmethod
+    def _result(r: Result, fetch: bool):
+        import numpy as np
+
+        out = dict(req_id=r.req_id, kind="insert" if r.kind == 0 else "refine", status=r.status, epoch=r.epoch,
+                   n_rows=r.n_rows, k=r.k, perplexity=r.perplexity, n_changed=r.n_changed,
+                   t_submit_ms=r.t_submit_ms, t_admit_ms=r.t_admit_ms, t_complete_ms=r.t_complete_ms)
+        if fetch and r.status == OK:
+            n, k = r.n_rows, r.k
+            out["row_ids"] = _d2h(r.row_ids, (n,), np.int32)
+            out["idx"] = _d2h(r.nbr_idx, (n, k), np.int32)
+            out["d2"] = _d2h(r.nbr_d2, (n, k), np.float32)
+            out["P"] = _d2h(r.P_cond, (n, k), np.float32)
+            out["beta"] = _d2h(r.beta, (n,), np.float32)
+            out["flags"] = _d2h(r.flags, (n,), np.uint8)
+            if r.kind == 0:
+                out["changed"] = _d2h(r.changed, (r.n_changed,), np.int32)
+        return out
+
+    def poll(self, rid: int, fetch: bool = True):
+        r = Result()
+        st = load().atsne_serve_poll(self.h, rid, ctypes.byref(r))
+        if st == E_BUSY:
+            return None
+        _check(st)
+        return self._result(r, fetch)
+
+    def wait(self, rid: int, fetch: bool = True):
+        r = Result()
+        _check(load().atsne_serve_wait(self.h, rid, ctypes.byref(r)))
+        return self._result(r, fetch)
+
+    def release(self, rid: int):
+        _check(load().atsne_serve_release(self.h, rid))
+
+    def stats(self):
+        st = ServeStats()
+        _check(load().atsne_serve_stats_get(self.h, ctypes.byref(st)))
+        return {name: getattr(st, name) for name, _ in ServeStats._fields_}
+
+    def snapshot(self):
+        """(corpus, idx, d2) numpy copies of the committed state."""
+        import numpy as np
+
+        st = self.stats()
+        cap = st["corpus_rows"]
+        K = int(math.floor(3 * self.perplexity))
+        X = torch.empty((cap, self.D), dtype=torch.float32, device="cuda")
+        idx = torch.empty((cap, K), dtype=torch.int32, device="cuda")
+        d2 = torch.empty((cap, K), dtype=torch.float32, device="cuda")
+        n, ep = ctypes.c_int64(), ctypes.c_uint64()
+        _check(load().atsne_serve_snapshot(self.h, cap, _ptr(X), _ptr(idx), _ptr(d2), ctypes.byref(n),
+                                           ctypes.byref(ep)))
+        n = n.value
+        return X[:n].cpu().numpy(), idx[:n].cpu().numpy(), d2[:n].cpu().numpy()
+
+    def close(self, force: bool = True):
+        if getattr(self, "h", None):
+            _check(load().atsne_serve_destroy(self.h, 1 if force else 0))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close(True)
+        except Exception:
+            pass

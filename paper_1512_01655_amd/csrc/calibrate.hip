@@ -14,22 +14,28 @@
 #include <cmath>
 #include <vector>
 
-#include "common.h"
+#include "knn_internal.h"
 #include "wave.h"
 
 namespace atsne {
 
 constexpr int CAL_MAXR = 16;  // k <= 1024
 
+// Row r of the launch is table row (row_ids ? row_ids[r] : r); rows at or
+// beyond *n_rows_dev (when given) are skipped.  Distance and P rows have
+// stride `stride`.
 template <int R>
-__global__ __launch_bounds__(256) void calibrate_rows(const float* __restrict__ d2, int64_t N, int k, float mu,
-                                                      float tol, int max_iter, float* __restrict__ P,
+__global__ __launch_bounds__(256) void calibrate_rows(const float* __restrict__ d2, int64_t stride,
+                                                      const int32_t* __restrict__ row_ids,
+                                                      const int32_t* __restrict__ n_rows_dev, int64_t N, int k,
+                                                      float mu, float tol, int max_iter, float* __restrict__ P,
                                                       float* __restrict__ beta_out, float* __restrict__ perp_out,
                                                       uint8_t* __restrict__ flags) {
     const int l = lane_id();
-    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (row >= N) return;
-    const float* d = d2 + row * k;
+    const int64_t r_ = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r_ >= N || (n_rows_dev && r_ >= *n_rows_dev)) return;
+    const int64_t row = row_ids ? (int64_t)row_ids[r_] : r_;
+    const float* d = d2 + row * stride;
     float dl[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -120,7 +126,7 @@ __global__ __launch_bounds__(256) void calibrate_rows(const float* __restrict__ 
         int c = l + WAVE * r;
         if (c < k) {
             float p = w[r] * invZ;
-            P[row * k + c] = p;
+            P[row * stride + c] = p;
             if (p > 0.f) ent -= p * logf(p);
         }
     }
@@ -130,6 +136,31 @@ __global__ __launch_bounds__(256) void calibrate_rows(const float* __restrict__ 
         if (perp_out) perp_out[row] = expf(ent);
         if (flags) flags[row] |= fl;
     }
+}
+
+atsne_status calibrate_table(const float* d2, int64_t stride, const int32_t* row_ids, const int32_t* n_rows_dev,
+                             int64_t n_rows, int k, float mu, float tol, int max_iter, float* P, float* beta,
+                             float* perp, uint8_t* flags, hipStream_t st) {
+    if (n_rows == 0) return ATSNE_OK;
+    const dim3 grid((unsigned)ceil_div(n_rows, 4)), block(256);
+    const int R = (k + 63) / 64;
+    ProfScope ps_("calibrate_rows", st);
+#define ATSNE_CAL(RR)                                                                                      \
+    calibrate_rows<RR><<<grid, block, 0, st>>>(d2, stride, row_ids, n_rows_dev, n_rows, k, mu, tol, max_iter, P, \
+                                               beta, perp, flags)
+    if (R <= 1)
+        ATSNE_CAL(1);
+    else if (R <= 2)
+        ATSNE_CAL(2);
+    else if (R <= 4)
+        ATSNE_CAL(4);
+    else if (R <= 8)
+        ATSNE_CAL(8);
+    else
+        ATSNE_CAL(16);
+#undef ATSNE_CAL
+    ATSNE_LAUNCH_CHECK();
+    return ATSNE_OK;
 }
 
 }  // namespace atsne
@@ -149,23 +180,8 @@ extern "C" atsne_status atsne_calibrate_p(const float* nbr_d2, int64_t N, int32_
     if (max_iter <= 0) max_iter = 200;
     if (N == 0) return ATSNE_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const dim3 grid((unsigned)ceil_div(N, 4)), block(256);
-    const int R = (k + 63) / 64;
-    {
-    ProfScope ps_("calibrate_rows", st);
-    if (R <= 1)
-        calibrate_rows<1><<<grid, block, 0, st>>>(nbr_d2, N, k, perplexity, tol, max_iter, P_cond, beta, perp, flags);
-    else if (R <= 2)
-        calibrate_rows<2><<<grid, block, 0, st>>>(nbr_d2, N, k, perplexity, tol, max_iter, P_cond, beta, perp, flags);
-    else if (R <= 4)
-        calibrate_rows<4><<<grid, block, 0, st>>>(nbr_d2, N, k, perplexity, tol, max_iter, P_cond, beta, perp, flags);
-    else if (R <= 8)
-        calibrate_rows<8><<<grid, block, 0, st>>>(nbr_d2, N, k, perplexity, tol, max_iter, P_cond, beta, perp, flags);
-    else
-        calibrate_rows<16><<<grid, block, 0, st>>>(nbr_d2, N, k, perplexity, tol, max_iter, P_cond, beta, perp,
-                                                   flags);
-    ATSNE_LAUNCH_CHECK();
-    }
+    ATSNE_TRY(calibrate_table(nbr_d2, k, nullptr, nullptr, N, k, perplexity, tol, max_iter, P_cond, beta, perp, flags,
+                              st));
     if (strict) {
         std::vector<uint8_t> h((size_t)N);
         ATSNE_HIP(hipMemcpyAsync(h.data(), flags, (size_t)N, hipMemcpyDeviceToHost, st));

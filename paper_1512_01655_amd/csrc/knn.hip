@@ -25,7 +25,7 @@
 #include <algorithm>
 #include <cmath>
 
-#include "common.h"
+#include "knn_internal.h"
 #include "wave.h"
 
 namespace atsne {
@@ -35,7 +35,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 
 constexpr int QB = 128;         // queries per workgroup (4 waves x 32)
-constexpr int KT = 256;         // keys per tile (8 MFMA blocks of 32)
+constexpr int KT = KNN_KT;      // keys per tile (8 MFMA blocks of 32)
 constexpr int NKB = KT / 32;    // key blocks per tile
 constexpr int CHUNK_UNITS = 8;  // 16-byte units per row per D-chunk (128 bytes)
 constexpr int ROW_UNITS = 9;    // LDS row stride in 16-byte units (one unit of padding)
@@ -87,17 +87,16 @@ __device__ __forceinline__ float e4m3_to_f32(uint8_t b) {
 }
 
 // ---------------------------------------------------------------------------
-// knn_prep: one wave per row.
+// knn_prep: one wave per row of [r0, r1); rows >= n_live are zero padding.
 // ---------------------------------------------------------------------------
 template <int P>
-__global__ __launch_bounds__(256) void knn_prep(const float* __restrict__ X, int64_t N, int32_t D, int64_t ld,
-                                                int64_t N_pad, int32_t Dp, void* __restrict__ Xp,
-                                                float* __restrict__ norms, float* __restrict__ scales,
-                                                uint32_t* __restrict__ nmax_bits) {
+__global__ __launch_bounds__(256) void knn_prep(const float* __restrict__ X, int64_t ld, int32_t D, int32_t Dp,
+                                                int64_t r0, int64_t r1, int64_t n_live, void* __restrict__ Xp,
+                                                float* __restrict__ norms, float* __restrict__ scales) {
     const int l = lane_id();
-    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (row >= N_pad) return;
-    const bool live = row < N;
+    const int64_t row = r0 + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= r1) return;
+    const bool live = row < n_live;
     const float* x = X + row * ld;
     float s = 1.0f;
     if (P == ATSNE_PREC_FP8_E4M3) {
@@ -130,8 +129,51 @@ __global__ __launch_bounds__(256) void knn_prep(const float* __restrict__ X, int
     if (l == 0) {
         norms[row] = live ? acc : 0.0f;
         scales[row] = s;
-        if (live) atomicMax(nmax_bits, __float_as_uint(acc));  // non-negative floats order as uints
     }
+}
+
+// Prefix maximum of the norms over [r0, r1), continuing from pmax[r0 - 1].
+// One workgroup walks the range in chunks of 1024 rows.
+__global__ __launch_bounds__(1024) void knn_pmax(const float* __restrict__ norms, float* __restrict__ pmax,
+                                                 int64_t r0, int64_t r1) {
+    __shared__ float wmax[16];
+    __shared__ float carry_s;
+    const int t = threadIdx.x, l = t & 63, w = t >> 6;
+    if (t == 0) carry_s = r0 > 0 ? pmax[r0 - 1] : 0.0f;
+    __syncthreads();
+    for (int64_t base = r0; base < r1; base += 1024) {
+        const int64_t i = base + t;
+        float v = i < r1 ? norms[i] : 0.0f;
+#pragma unroll
+        for (int o = 1; o < WAVE; o <<= 1) {
+            float u = __shfl_up(v, o, WAVE);
+            if (l >= o) v = fmaxf(v, u);
+        }
+        if (l == WAVE - 1) wmax[w] = v;
+        __syncthreads();
+        float pre = carry_s;
+        for (int j = 0; j < w; ++j) pre = fmaxf(pre, wmax[j]);
+        v = fmaxf(v, pre);
+        if (i < r1) pmax[i] = v;
+        __syncthreads();
+        if (t == 1023) carry_s = v;
+        __syncthreads();
+    }
+}
+
+// Rigorous bound on |d'_qj + n_q - ||x_q - x_j||^2| for the FP32 contraction:
+// with gam = (Dp + 2) u for sums of Dp products,
+// |fl(n_j) - n_j| + 2|fl(S_qj) - S_qj| + |fl(n_q) - n_q| <= gam (sqrt(n_q) + sqrt(n_j))^2,
+// plus the rounding of forming d' and adding n_q back.
+__device__ __forceinline__ float fp32_contraction_bound(int32_t Dp, float nq, float nmax, float dprime) {
+    const float u = 5.9604645e-8f;
+    const float gam = 1.05f * (float)(Dp + 2) * u;
+    const float sq = sqrtf(nq) + sqrtf(nmax);
+    return gam * (sq * sq) + 2.0f * u * (fabsf(dprime) + nq);
+}
+
+__device__ __forceinline__ int64_t load_qid(const int32_t* qids, int64_t m0, int64_t m) {
+    return qids ? (int64_t)qids[m] : (m0 + m);
 }
 
 // ---------------------------------------------------------------------------
@@ -204,12 +246,31 @@ __device__ uint64_t shrink_slot(uint64_t* slot, int cnt, int kc, uint32_t* hist)
 // query block) with the query block fastest, so the workgroups that share an
 // XCD (dispatched round-robin) stream the same key tiles through its L2.
 // ---------------------------------------------------------------------------
+struct TileArgs {
+    const uint4* Xp;
+    int64_t row_units;
+    int n_chunks;
+    int32_t Dp;
+    const float* norms;
+    const float* scales;
+    const float* pmax;
+    int64_t M;
+    const int32_t* qids;
+    int64_t m0;
+    const int32_t* nlims;
+    int64_t nlim;
+    int64_t key_lo;
+    const int32_t* kcs;
+    int kc;
+    const float* tau0;
+    int64_t tau0_stride;
+    int MB, S, tiles_per_split, tile_lo, tile_hi, cap;
+    uint64_t* slots;
+    int32_t* counts;
+};
+
 template <int P>
-__global__ __launch_bounds__(TILE_THREADS) __attribute__((amdgpu_waves_per_eu(1, 1))) void knn_tile(
-    const uint4* __restrict__ Xp, int64_t row_units, int n_chunks, const float* __restrict__ norms,
-    const float* __restrict__ scales, int64_t N, const int32_t* __restrict__ qids, int64_t m0, int64_t Mb, int MB,
-    int S, int tiles_per_split, int total_tiles, int kc, int cap, uint64_t* __restrict__ slots,
-    int32_t* __restrict__ counts) {
+__global__ __launch_bounds__(TILE_THREADS) __attribute__((amdgpu_waves_per_eu(1, 1))) void knn_tile(TileArgs a) {
     __shared__ uint4 Ks[KT * ROW_UNITS];
     __shared__ uint4 Qs[QB * ROW_UNITS];
     __shared__ float Kn[KT];
@@ -219,11 +280,12 @@ __global__ __launch_bounds__(TILE_THREADS) __attribute__((amdgpu_waves_per_eu(1,
     const int t = threadIdx.x;
     const int l = t & 63;
     const int w = t >> 6;
-    const int qb = blockIdx.x % MB;
-    const int split = blockIdx.x / MB;
-    const int tile_begin = split * tiles_per_split;
-    const int tile_end = min(total_tiles, tile_begin + tiles_per_split);
+    const int qb = blockIdx.x % a.MB;
+    const int split = blockIdx.x / a.MB;
+    const int tile_begin = a.tile_lo + split * a.tiles_per_split;
+    const int tile_end = min(a.tile_hi, tile_begin + a.tiles_per_split);
     uint32_t* hist = hist_all[w];
+    const int64_t row_units = a.row_units;
 
     // Rows of the query tile this thread loads (4 rows, unit t & 7).
     int64_t qrow_off[4];
@@ -231,30 +293,43 @@ __global__ __launch_bounds__(TILE_THREADS) __attribute__((amdgpu_waves_per_eu(1,
     for (int i = 0; i < 4; ++i) {
         int r = (t >> 3) + 32 * i;
         int64_t m = (int64_t)qb * QB + r;
-        int64_t row = 0;
-        if (m < Mb) row = qids ? (int64_t)qids[m0 + m] : (m0 + m);
+        int64_t row = m < a.M ? load_qid(a.qids, a.m0, m) : 0;
         qrow_off[i] = row * row_units + (t & 7);
     }
 
     // Per-lane query state (lanes l and l+32 share query 32w + l%32).
     const int qloc = 32 * w + (l & 31);
     const int64_t mq = (int64_t)qb * QB + qloc;
-    const bool qvalid = mq < Mb;
-    const int64_t self = qvalid ? (qids ? (int64_t)qids[m0 + mq] : (m0 + mq)) : -1;
-    const float qscale = (P == ATSNE_PREC_FP8_E4M3 && qvalid) ? scales[self] : 1.0f;
-    uint64_t* myslot = slots + ((size_t)(qvalid ? mq : 0) * S + split) * (size_t)cap;
-    float tau = qvalid ? INFINITY : -INFINITY;
+    const bool qvalid = mq < a.M;
+    const int64_t self = qvalid ? load_qid(a.qids, a.m0, mq) : -1;
+    const int64_t nl = qvalid ? (a.nlims ? (int64_t)a.nlims[mq] : a.nlim) : 0;
+    const int kcq = qvalid ? (a.kcs ? a.kcs[mq] : a.kc) : 0;
+    const float qscale = (P == ATSNE_PREC_FP8_E4M3 && qvalid) ? a.scales[self] : 1.0f;
+    uint64_t* myslot = a.slots + ((size_t)(qvalid ? mq : 0) * a.S + split) * (size_t)a.cap;
+    float tau = -INFINITY;
+    if (qvalid) {
+        tau = INFINITY;
+        if (a.tau0) {
+            // reverse mode: only keys that may beat the row's farthest
+            // neighbour; d' = d - n_q, widened by the contraction bound
+            const float nq = a.norms[self];
+            const float nmax = nl > 0 ? a.pmax[nl - 1] : 0.0f;
+            const float dmax = a.tau0[mq * a.tau0_stride];
+            tau = dmax - nq + fp32_contraction_bound(a.Dp, nq, nmax, dmax) * 2.0f + 1e-30f;
+        }
+    }
     int count = 0;
 
     uint4 pk[8], pq[4];
     auto load_chunk = [&](int tile, int c) {
-        const uint4* kbase = Xp + (int64_t)tile * KT * row_units + (int64_t)c * CHUNK_UNITS;
+        const uint4* kbase = a.Xp + (int64_t)tile * KT * row_units + (int64_t)c * CHUNK_UNITS;
 #pragma unroll
         for (int i = 0; i < 8; ++i) pk[i] = kbase[(int64_t)((t >> 3) + 32 * i) * row_units + (t & 7)];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) pq[i] = Xp[qrow_off[i] + (int64_t)c * CHUNK_UNITS];
+        for (int i = 0; i < 4; ++i) pq[i] = a.Xp[qrow_off[i] + (int64_t)c * CHUNK_UNITS];
     };
 
+    const int n_chunks = a.n_chunks;
     if (tile_begin < tile_end) load_chunk(tile_begin, 0);
     for (int tile = tile_begin; tile < tile_end; ++tile) {
         f32x16 acc[NKB];
@@ -270,8 +345,8 @@ __global__ __launch_bounds__(TILE_THREADS) __attribute__((amdgpu_waves_per_eu(1,
 #pragma unroll
             for (int i = 0; i < 4; ++i) Qs[((t >> 3) + 32 * i) * ROW_UNITS + (t & 7)] = pq[i];
             if (c == 0) {
-                Kn[t] = norms[(int64_t)tile * KT + t];
-                if (P == ATSNE_PREC_FP8_E4M3) Ksc[t] = scales[(int64_t)tile * KT + t];
+                Kn[t] = a.norms[(int64_t)tile * KT + t];
+                if (P == ATSNE_PREC_FP8_E4M3) Ksc[t] = a.scales[(int64_t)tile * KT + t];
             }
             __syncthreads();
             if (c + 1 < n_chunks)
@@ -293,16 +368,17 @@ __global__ __launch_bounds__(TILE_THREADS) __attribute__((amdgpu_waves_per_eu(1,
 
         // ---- epilogue: make room, then filter this tile's candidates ----
         {
-            uint64_t need = ballot(count > cap - KT) & 0xffffffffull;
+            uint64_t need = ballot(count > a.cap - KT) & 0xffffffffull;
             while (need) {
                 int q = __ffsll((unsigned long long)need) - 1;
                 need &= need - 1;
                 int cnt_q = __shfl(count, q, WAVE);
-                uint64_t* sq = slots + ((size_t)((int64_t)qb * QB + 32 * w + q) * S + split) * (size_t)cap;
-                uint64_t kstar = shrink_slot(sq, cnt_q, kc, hist);
+                int kc_q = __shfl(kcq, q, WAVE);
+                uint64_t* sq = a.slots + ((size_t)((int64_t)qb * QB + 32 * w + q) * a.S + split) * (size_t)a.cap;
+                uint64_t kstar = shrink_slot(sq, cnt_q, kc_q, hist);
                 if ((l & 31) == q) {
-                    count = kc;
-                    tau = key_dist(kstar);
+                    count = kc_q;
+                    tau = fminf(tau, key_dist(kstar));
                 }
             }
         }
@@ -325,7 +401,7 @@ __global__ __launch_bounds__(TILE_THREADS) __attribute__((amdgpu_waves_per_eu(1,
                         s *= qscale * sje;
                     }
                     const float d = fmaf(-2.0f, s, nje);
-                    const bool pass = (d < tau) && (key < N) && (key != self);
+                    const bool pass = (d < tau) && (key >= a.key_lo) && (key < nl) && (key != self);
                     const uint64_t m = ballot(pass);
                     if (m) {
                         const uint32_t lo = (uint32_t)m, hi = (uint32_t)(m >> 32);
@@ -340,19 +416,20 @@ __global__ __launch_bounds__(TILE_THREADS) __attribute__((amdgpu_waves_per_eu(1,
         }
     }
 
-    // Final shrink so each slot hands at most kc candidates to knn_select.
+    // Final shrink so each slot hands at most kc candidates to the next stage.
     {
-        uint64_t need = ballot(count > kc) & 0xffffffffull;
+        uint64_t need = ballot(count > kcq) & 0xffffffffull;
         while (need) {
             int q = __ffsll((unsigned long long)need) - 1;
             need &= need - 1;
             int cnt_q = __shfl(count, q, WAVE);
-            uint64_t* sq = slots + ((size_t)((int64_t)qb * QB + 32 * w + q) * S + split) * (size_t)cap;
-            (void)shrink_slot(sq, cnt_q, kc, hist);
-            if ((l & 31) == q) count = kc;
+            int kc_q = __shfl(kcq, q, WAVE);
+            uint64_t* sq = a.slots + ((size_t)((int64_t)qb * QB + 32 * w + q) * a.S + split) * (size_t)a.cap;
+            (void)shrink_slot(sq, cnt_q, kc_q, hist);
+            if ((l & 31) == q) count = kc_q;
         }
     }
-    if (qvalid && l < 32) counts[mq * S + split] = count;
+    if (qvalid && l < 32) a.counts[mq * a.S + split] = count;
 }
 
 // ---------------------------------------------------------------------------
@@ -464,14 +541,52 @@ __device__ void direct_distances(const float* __restrict__ X, int64_t ld, int32_
 
 constexpr int MAX_KC = 1024;
 
-// knn_select: one wave (workgroup of 64) per query.
+struct SelArgs {
+    const float* X;
+    int64_t ld;
+    int32_t D, Dp;
+    const float* norms;
+    const float* pmax;
+    int64_t M;
+    const int32_t* qids;
+    int64_t m0;
+    const int32_t* nlims;
+    int64_t nlim;
+    int64_t key_lo;
+    const int32_t* ks;
+    int k;
+    const int32_t* kcs;
+    int kc;
+    int S, cap;
+    const uint64_t* slots;
+    const int32_t* counts;
+    int32_t* out_idx;
+    float* out_d2;
+    uint8_t* out_flags;
+    int64_t out_stride;
+    int32_t* scan_list;
+    int32_t* scan_count;
+};
+
+// Gathers the union of a row's candidate slots; returns the threshold key
+// (rank `take`) so that exactly the keys <= it are the candidates.
+template <class Each>
+__device__ uint64_t union_threshold(Each each, int take, int total, uint32_t* hist) {
+    const int l = lane_id();
+    if (take < total) return wave_select(each, (uint32_t)take, hist);
+    uint64_t mx = 0;
+    each([&](uint64_t key) { mx = key > mx ? key : mx; });
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        uint64_t other = shfl64(mx, l ^ o);
+        mx = other > mx ? other : mx;
+    }
+    return mx;
+}
+
+// knn_select: one wave (workgroup of 64) per query row.
 template <int P>
-__global__ __launch_bounds__(64) void knn_select(
-    const float* __restrict__ X, int64_t ld, int32_t D, int64_t N, const int32_t* __restrict__ qids, int64_t m0,
-    int64_t Mb, int S, int cap, int kc, int k, const uint64_t* __restrict__ slots, const int32_t* __restrict__ counts,
-    const float* __restrict__ norms, const uint32_t* __restrict__ nmax_bits, int32_t Dp,
-    int32_t* __restrict__ nbr_idx, float* __restrict__ nbr_d2, uint8_t* __restrict__ flags,
-    int32_t* __restrict__ scan_list, int32_t* __restrict__ scan_count) {
+__global__ __launch_bounds__(64) void knn_select(SelArgs a) {
     __shared__ uint32_t hist[256];
     __shared__ int32_t cj[MAX_KC];
     __shared__ float cd[MAX_KC];
@@ -480,35 +595,27 @@ __global__ __launch_bounds__(64) void knn_select(
     __shared__ int32_t ncand;
     const int l = lane_id();
     const int64_t m = blockIdx.x;
-    if (m >= Mb) return;
-    const int64_t q = qids ? (int64_t)qids[m0 + m] : (m0 + m);
-    const int32_t* cnt = counts + m * S;
-    const uint64_t* base = slots + (size_t)m * S * (size_t)cap;
+    if (m >= a.M) return;
+    const int64_t q = load_qid(a.qids, a.m0, m);
+    const int64_t nl = a.nlims ? (int64_t)a.nlims[m] : a.nlim;
+    const int k = a.ks ? a.ks[m] : a.k;
+    const int kc = a.kcs ? a.kcs[m] : a.kc;
+    const int32_t* cnt = a.counts + m * a.S;
+    const uint64_t* base = a.slots + (size_t)m * a.S * (size_t)a.cap;
+    int32_t* out_idx = a.out_idx + m * a.out_stride;
+    float* out_d2 = a.out_d2 + m * a.out_stride;
 
     int total = 0;
-    for (int s = 0; s < S; ++s) total += cnt[s];
+    for (int s = 0; s < a.S; ++s) total += cnt[s];
     const int take = min(kc, total);
     auto each = [&](auto f) {
-        for (int s = 0; s < S; ++s) {
-            const uint64_t* sl = base + (size_t)s * cap;
+        for (int s = 0; s < a.S; ++s) {
+            const uint64_t* sl = base + (size_t)s * a.cap;
             const int c = cnt[s];
             for (int i = l; i < c; i += WAVE) f(sl[i]);
         }
     };
-    uint64_t kstar;
-    if (take < total) {
-        kstar = wave_select(each, (uint32_t)take, hist);
-    } else {
-        // every entry is a candidate: the threshold is the largest key held
-        uint64_t mx = 0;
-        each([&](uint64_t key) { mx = key > mx ? key : mx; });
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) {
-            uint64_t other = shfl64(mx, l ^ o);
-            mx = other > mx ? other : mx;
-        }
-        kstar = mx;
-    }
+    const uint64_t kstar = union_threshold(each, take, total, hist);
     if (l == 0) ncand = 0;
     wave_sync();
     each([&](uint64_t key) {
@@ -519,63 +626,60 @@ __global__ __launch_bounds__(64) void knn_select(
     });
     wave_sync();
     const int n = ncand;
-    const float* xq = X + q * ld;
-    direct_distances(X, ld, D, xq, n, cj, cd);
+    const float* xq = a.X + q * a.ld;
+    direct_distances(a.X, a.ld, a.D, xq, n, cj, cd);
+    if (n < k) {  // fewer keys than requested neighbours (caller error): pad
+        for (int r = l; r < k; r += WAVE) {
+            out_idx[r] = -1;
+            out_d2[r] = INFINITY;
+        }
+    }
 
     uint8_t extra = 0;
-    if (P == ATSNE_PREC_FP32 && take < (int)(N - 1)) {
-        // Certificate: every non-candidate j has d'_j >= d'(kstar); its true
-        // distance is at least d'(kstar) + n_q - E, E bounding the FP32
-        // contraction error.  If that exceeds the k-th exact distance (with
-        // the direct-difference error), no non-candidate can be a neighbour.
-        // |fl(n_j) - n_j| + 2|fl(S_qj) - S_qj| + |fl(n_q) - n_q| <= gam (n_j + 2 sqrt(n_q n_j) + n_q)
-        // with gam = (Dp + 2) u for sums of Dp products, n_j <= n_max.
-        const float u = 5.9604645e-8f;
-        const float nq = norms[q];
-        const float nmax = __uint_as_float(*nmax_bits);
-        const float gam = 1.05f * (float)(Dp + 2) * u;
-        const float sq = sqrtf(nq) + sqrtf(nmax);
-        float dk = 0.f;
-        // k-th smallest exact distance among the candidates
+    const int64_t n_valid = max<int64_t>(0, nl - a.key_lo) - ((q >= a.key_lo && q < nl) ? 1 : 0);
+    if (P == ATSNE_PREC_FP32 && take < n_valid && n >= k) {
+        // Certificate: every non-candidate j has d'_j >= d'(kstar), so its
+        // true distance is at least d'(kstar) + n_q - E.  If that exceeds the
+        // (k+1)-th exact candidate distance (plus the direct-difference
+        // error), the candidates hold the true k+1 nearest and the row's
+        // ranking, tie decision included, is that of a full scan.
+        const int rk = n > k ? k : k - 1;
         for (int c = l; c < n; c += WAVE) {
             uint64_t kc_ = pack_key(cd[c], cj[c]);
             int r = 0;
             for (int o = 0; o < n; ++o) r += pack_key(cd[o], cj[o]) < kc_;
-            if (r == k - 1) sorted[0] = kc_;
+            if (r == rk) sorted[0] = kc_;
         }
         wave_sync();
-        dk = key_dist(sorted[0]);
+        const float dk = key_dist(sorted[0]);
         wave_sync();
+        const float nq = a.norms[q];
+        const float nmax = nl > 0 ? a.pmax[nl - 1] : 0.0f;
         const float dthr = key_dist(kstar);
-        const float E = gam * (sq * sq) + 2.0f * u * (fabsf(dthr) + nq);
-        const float lb = dthr + nq - E;
+        const float lb = dthr + nq - fp32_contraction_bound(a.Dp, nq, nmax, dthr);
         if (!(lb > dk * (1.0f + 2.0f * TIE_REL))) {
             extra = ATSNE_FLAG_EXACT_SCAN;
             if (l == 0) {
-                int p = atomicAdd(scan_count, 1);
-                scan_list[p] = (int32_t)m;
+                int p = atomicAdd(a.scan_count, 1);
+                a.scan_list[p] = (int32_t)m;
             }
         }
     }
-    finalize_row(X, ld, D, xq, n, k, cj, cd, sorted, dd, nbr_idx + m * k, nbr_d2 + m * k,
-                 flags ? flags + m : nullptr, extra);
+    if (n >= k)
+        finalize_row(a.X, a.ld, a.D, xq, n, k, cj, cd, sorted, dd, out_idx, out_d2,
+                     a.out_flags ? a.out_flags + m : nullptr, extra);
 }
 
 // knn_scan: exact FP32 linear scan for rows whose candidate margin was not
 // certified.  One workgroup (4 waves) per queued row, persistent over the
 // queue; every workgroup exits once the queue is drained.  Each wave scans
-// the keys j = w, w+4, ... in increasing order with the same direct-difference
-// arithmetic as knn_select, keeps (d, j) keys below its running threshold in
-// an LDS region and shrinks the region to its best SCAN_KEEP keys when full;
-// keys arrive in increasing j, so after a shrink a strict d < tau filter is
-// exact.  The four regions are merged at the end.
+// the keys j = key_lo + w, +4, ... in increasing order with the same
+// direct-difference arithmetic as knn_select, keeps (d, j) keys at or below
+// its running threshold in an LDS region and shrinks the region to its best
+// `keep` keys when full; keys arrive in increasing j, so after a shrink a
+// strict d < tau filter is exact.  The four regions are merged at the end.
 constexpr int SCAN_REGION = 1024;
-__global__ __launch_bounds__(256) void knn_scan(const float* __restrict__ X, int64_t ld, int32_t D, int64_t N,
-                                                const int32_t* __restrict__ qids, int64_t m0, int k, int keep,
-                                                const int32_t* __restrict__ scan_list,
-                                                const int32_t* __restrict__ scan_count, int32_t* __restrict__ cursor,
-                                                int32_t* __restrict__ nbr_idx, float* __restrict__ nbr_d2,
-                                                uint8_t* __restrict__ flags) {
+__global__ __launch_bounds__(256) void knn_scan(SelArgs a, int keep_extra, int32_t* __restrict__ cursor) {
     __shared__ uint64_t region[4][SCAN_REGION];
     __shared__ uint32_t hist_all[4][256];
     __shared__ int32_t rcount[4];
@@ -585,7 +689,7 @@ __global__ __launch_bounds__(256) void knn_scan(const float* __restrict__ X, int
     __shared__ double dd[MAX_KC];
     __shared__ int32_t item;
     const int t = threadIdx.x, l = t & 63, w = t >> 6;
-    const int nq = *scan_count;
+    const int nq = *a.scan_count;
     uint64_t* reg = region[w];
     uint32_t* hist = hist_all[w];
     for (;;) {
@@ -594,34 +698,39 @@ __global__ __launch_bounds__(256) void knn_scan(const float* __restrict__ X, int
         __syncthreads();
         const int it = item;
         if (it >= nq) break;
-        const int64_t m = scan_list[it];
-        const int64_t q = qids ? (int64_t)qids[m0 + m] : (m0 + m);
-        const float* xq = X + q * ld;
+        const int64_t m = a.scan_list[it];
+        const int64_t q = load_qid(a.qids, a.m0, m);
+        const int64_t nl = a.nlims ? (int64_t)a.nlims[m] : a.nlim;
+        const int k = a.ks ? a.ks[m] : a.k;
+        const int keep = min(k + keep_extra, SCAN_REGION - 24);
+        int32_t* out_idx = a.out_idx + m * a.out_stride;
+        float* out_d2 = a.out_d2 + m * a.out_stride;
+        const float* xq = a.X + q * a.ld;
         // The current k-th exact distance bounds the true k-th from above.
-        float tau = nbr_d2[m * k + (k - 1)];
+        float tau = out_d2[k - 1];
         bool strict = false;
         int cnt = 0;
-        for (int64_t j0 = w; j0 < N; j0 += 16) {
-            float a[4];
+        for (int64_t j0 = a.key_lo + w; j0 < nl; j0 += 16) {
+            float dj[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int64_t j = j0 + 4 * u;
                 float acc = 0.f;
-                if (j < N) {
-                    const float* xj = X + j * ld;
-                    for (int d = l; d < D; d += WAVE) {
+                if (j < nl) {
+                    const float* xj = a.X + j * a.ld;
+                    for (int d = l; d < a.D; d += WAVE) {
                         float tt = xq[d] - xj[d];
                         acc = fmaf(tt, tt, acc);
                     }
                 }
-                a[u] = wave_sum(acc);
+                dj[u] = wave_sum(acc);
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int64_t j = j0 + 4 * u;
-                const bool pass = j < N && j != q && (strict ? (a[u] < tau) : (a[u] <= tau));
+                const bool pass = j < nl && j != q && (strict ? (dj[u] < tau) : (dj[u] <= tau));
                 if (pass) {
-                    if (l == 0) reg[cnt] = pack_key(a[u], (int32_t)j);
+                    if (l == 0) reg[cnt] = pack_key(dj[u], (int32_t)j);
                     ++cnt;
                 }
             }
@@ -658,8 +767,7 @@ __global__ __launch_bounds__(256) void knn_scan(const float* __restrict__ X, int
                     for (int i = l; i < rcount[r]; i += WAVE) f(region[r][i]);
             };
             const int take = min(keep, tot);
-            uint64_t kstar = ~0ull;
-            if (take < tot) kstar = wave_select(each, (uint32_t)take, hist);
+            const uint64_t kstar = union_threshold(each, take, tot, hist);
             int n = 0;
             for (int r = 0; r < 4; ++r) {
                 for (int i0 = 0; i0 < rcount[r]; i0 += WAVE) {
@@ -677,27 +785,102 @@ __global__ __launch_bounds__(256) void knn_scan(const float* __restrict__ X, int
             }
             wave_sync();
             if (n >= k)
-                finalize_row(X, ld, D, xq, n, k, cj, cd, sorted, dd, nbr_idx + m * k, nbr_d2 + m * k,
-                             flags ? flags + m : nullptr, ATSNE_FLAG_EXACT_SCAN);
+                finalize_row(a.X, a.ld, a.D, xq, n, k, cj, cd, sorted, dd, out_idx, out_d2,
+                             a.out_flags ? a.out_flags + m : nullptr, ATSNE_FLAG_EXACT_SCAN);
         }
+    }
+}
+
+// knn_reverse_merge: one wave per resident row.  Its candidates are new rows
+// whose approximate distance may beat the row's farthest neighbour; the exact
+// FP32 distance decides (Eq. 13, strict), and the survivors are merged into
+// the row's list, keeping its k best by (d, j).
+struct RevArgs {
+    SelArgs s;
+    int32_t* res_idx;
+    float* res_d2;
+    uint8_t* res_flags;
+    int64_t res_stride;
+    int32_t* changed;
+    int32_t* n_changed;
+};
+
+__global__ __launch_bounds__(64) void knn_reverse_merge(RevArgs r) {
+    __shared__ uint32_t hist[256];
+    __shared__ int32_t cj[MAX_KC];
+    __shared__ float cd[MAX_KC];
+    __shared__ uint64_t sorted[MAX_KC];
+    __shared__ double dd[MAX_KC];
+    __shared__ int32_t ncand;
+    const SelArgs& a = r.s;
+    const int l = lane_id();
+    const int64_t m = blockIdx.x;
+    if (m >= a.M) return;
+    const int64_t q = load_qid(a.qids, a.m0, m);
+    const int k = a.k;
+    const int32_t* cnt = a.counts + m * a.S;
+    int total = 0;
+    for (int s = 0; s < a.S; ++s) total += cnt[s];
+    if (total == 0) return;
+    const uint64_t* base = a.slots + (size_t)m * a.S * (size_t)a.cap;
+    auto each = [&](auto f) {
+        for (int s = 0; s < a.S; ++s) {
+            const uint64_t* sl = base + (size_t)s * a.cap;
+            const int c = cnt[s];
+            for (int i = l; i < c; i += WAVE) f(sl[i]);
+        }
+    };
+    const int take = min(total, MAX_KC - k);
+    const uint64_t kstar = union_threshold(each, take, total, hist);
+    int32_t* ridx = r.res_idx + q * r.res_stride;
+    float* rd2 = r.res_d2 + q * r.res_stride;
+    if (l == 0) ncand = 0;
+    wave_sync();
+    each([&](uint64_t key) {
+        if (key <= kstar) {
+            int p = atomicAdd(&ncand, 1);
+            cj[k + p] = key_index(key);
+        }
+    });
+    wave_sync();
+    const int nc = ncand;
+    const float* xq = a.X + q * a.ld;
+    direct_distances(a.X, a.ld, a.D, xq, nc, cj + k, cd + k);
+    const float dmax = rd2[k - 1];
+    // keep the new keys strictly closer than the farthest neighbour
+    int c = 0;
+    for (int i0 = 0; i0 < nc; i0 += WAVE) {
+        const int i = i0 + l;
+        const bool kp = i < nc && cd[k + i] < dmax;
+        int32_t jj = kp ? cj[k + i] : 0;
+        float dv = kp ? cd[k + i] : 0.f;
+        const uint64_t mm = ballot(kp);
+        wave_sync();
+        if (kp) {
+            const int p = c + __popcll(mm & lanemask_lt());
+            cj[k + p] = jj;
+            cd[k + p] = dv;
+        }
+        c += __popcll(mm);
+        wave_sync();
+    }
+    if (c == 0) return;
+    for (int i = l; i < k; i += WAVE) {
+        cj[i] = ridx[i];
+        cd[i] = rd2[i];
+    }
+    wave_sync();
+    finalize_row(a.X, a.ld, a.D, xq, k + c, k, cj, cd, sorted, dd, ridx, rd2,
+                 r.res_flags ? r.res_flags + q : nullptr, 0);
+    if (l == 0) {
+        const int p = atomicAdd(r.n_changed, 1);
+        r.changed[p] = (int32_t)q;
     }
 }
 
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
-struct KnnPlan {
-    int prec;
-    int64_t N, M, N_pad;
-    int32_t D, Dp;
-    int k, kc, cap;
-    int n_chunks, total_tiles;
-    int64_t Mb;  // queries per batch
-    int MB, S, tiles_per_split;
-    size_t b_xp, b_norm, b_scale, b_misc, b_slots, b_counts, b_list;
-    size_t total;
-};
-
 static int default_kcand(int prec, int k) {
     if (prec == ATSNE_PREC_FP32) return k + std::max(32, k / 2);
     return 2 * k;
@@ -720,6 +903,238 @@ static int pick_splits(int64_t MB, int total_tiles, int slots_avail) {
     return best_s;
 }
 
+size_t corpus_bytes(int prec, int64_t rows_cap, int32_t D) {
+    const int ce = chunk_elems(prec);
+    const int64_t Dp = ceil_div(D, ce) * ce;
+    const int64_t rows = ceil_div(std::max<int64_t>(rows_cap, 1), KT) * KT;
+    Arena a;
+    a.take<char>((size_t)rows * Dp * elem_bytes(prec));
+    a.take<float>(rows);
+    a.take<float>(rows);
+    a.take<float>(rows);
+    return a.used;
+}
+
+void corpus_bind(Corpus& c, int prec, const float* X, int64_t ld, int32_t D, int64_t rows_cap, void* mem) {
+    const int ce = chunk_elems(prec);
+    c.prec = prec;
+    c.X = X;
+    c.ld = ld;
+    c.D = D;
+    c.Dp = (int32_t)(ceil_div(D, ce) * ce);
+    c.n_chunks = c.Dp / ce;
+    c.row_units = (int64_t)c.Dp * elem_bytes(prec) / 16;
+    c.rows_cap = ceil_div(std::max<int64_t>(rows_cap, 1), KT) * KT;
+    Arena a(mem, corpus_bytes(prec, rows_cap, D));
+    c.Xp = a.take<char>((size_t)c.rows_cap * c.Dp * elem_bytes(prec));
+    c.norms = a.take<float>(c.rows_cap);
+    c.scales = a.take<float>(c.rows_cap);
+    c.pmax = a.take<float>(c.rows_cap);
+}
+
+atsne_status corpus_prep(const Corpus& c, int64_t r0, int64_t r1, int64_t n_live, hipStream_t st) {
+    if (r1 <= r0) return ATSNE_OK;
+    ProfScope ps_("knn_prep", st);
+    const dim3 grid((unsigned)ceil_div(r1 - r0, 4)), block(256);
+    switch (c.prec) {
+        case ATSNE_PREC_FP32:
+            knn_prep<ATSNE_PREC_FP32><<<grid, block, 0, st>>>(c.X, c.ld, c.D, c.Dp, r0, r1, n_live, c.Xp, c.norms,
+                                                              c.scales);
+            break;
+        case ATSNE_PREC_BF16:
+            knn_prep<ATSNE_PREC_BF16><<<grid, block, 0, st>>>(c.X, c.ld, c.D, c.Dp, r0, r1, n_live, c.Xp, c.norms,
+                                                              c.scales);
+            break;
+        default:
+            knn_prep<ATSNE_PREC_FP8_E4M3><<<grid, block, 0, st>>>(c.X, c.ld, c.D, c.Dp, r0, r1, n_live, c.Xp,
+                                                                  c.norms, c.scales);
+    }
+    ATSNE_LAUNCH_CHECK();
+    knn_pmax<<<dim3(1), dim3(1024), 0, st>>>(c.norms, c.pmax, r0, r1);
+    ATSNE_LAUNCH_CHECK();
+    return ATSNE_OK;
+}
+
+SearchPlan plan_search(int64_t M, int64_t key_lo, int64_t key_hi, int k_max, int kc_max, int s_max) {
+    SearchPlan p;
+    p.M = M;
+    p.k_max = k_max;
+    p.kc_max = kc_max;
+    p.tile_lo = (int)(key_lo / KT);
+    p.tile_hi = (int)ceil_div(key_hi, KT);
+    const int total_tiles = std::max(1, p.tile_hi - p.tile_lo);
+    p.cap = (int)align_up((size_t)(kc_max + KT + std::max(kc_max, 128)), 64);
+    p.MB = (int)ceil_div(std::max<int64_t>(M, 1), QB);
+    int S = pick_splits(p.MB, total_tiles, device_cu_count());
+    if (s_max > 0) S = std::min(S, s_max);
+    p.tiles_per_split = (int)ceil_div(total_tiles, S);
+    p.S = (int)ceil_div(total_tiles, p.tiles_per_split);
+    Arena a;
+    a.take<uint64_t>((size_t)p.MB * QB * p.S * p.cap);
+    a.take<int32_t>((size_t)p.MB * QB * p.S);
+    a.take<int32_t>(64);
+    a.take<int32_t>(std::max<int64_t>(M, 1));
+    p.ws_bytes = a.used;
+    return p;
+}
+
+struct SearchWs {
+    uint64_t* slots;
+    int32_t* counts;
+    int32_t* misc;
+    int32_t* scan_list;
+};
+
+static SearchWs carve(const SearchPlan& p, void* ws) {
+    Arena a(ws, p.ws_bytes);
+    SearchWs w;
+    w.slots = a.take<uint64_t>((size_t)p.MB * QB * p.S * p.cap);
+    w.counts = a.take<int32_t>((size_t)p.MB * QB * p.S);
+    w.misc = a.take<int32_t>(64);
+    w.scan_list = a.take<int32_t>(std::max<int64_t>(p.M, 1));
+    return w;
+}
+
+template <int P>
+static atsne_status launch_tile(const Corpus& c, const Batch& b, const SearchPlan& p, const SearchWs& w,
+                                hipStream_t st) {
+    TileArgs t;
+    t.Xp = static_cast<const uint4*>(c.Xp);
+    t.row_units = c.row_units;
+    t.n_chunks = c.n_chunks;
+    t.Dp = c.Dp;
+    t.norms = c.norms;
+    t.scales = c.scales;
+    t.pmax = c.pmax;
+    t.M = b.M;
+    t.qids = b.qids;
+    t.m0 = b.m0;
+    t.nlims = b.nlims;
+    t.nlim = b.nlim;
+    t.key_lo = b.key_lo;
+    t.kcs = b.kcs;
+    t.kc = b.kc;
+    t.tau0 = b.tau0;
+    t.tau0_stride = b.tau0_stride;
+    t.MB = (int)ceil_div(b.M, QB);
+    t.S = p.S;
+    t.tiles_per_split = p.tiles_per_split;
+    t.tile_lo = p.tile_lo;
+    t.tile_hi = p.tile_hi;
+    t.cap = p.cap;
+    t.slots = w.slots;
+    t.counts = w.counts;
+    ProfScope ps_(b.tau0 ? "knn_tile_reverse" : "knn_tile", st);
+    knn_tile<P><<<dim3((unsigned)(t.MB * p.S)), dim3(TILE_THREADS), 0, st>>>(t);
+    ATSNE_LAUNCH_CHECK();
+    return ATSNE_OK;
+}
+
+static atsne_status launch_tile_any(const Corpus& c, const Batch& b, const SearchPlan& p, const SearchWs& w,
+                                    hipStream_t st) {
+    switch (c.prec) {
+        case ATSNE_PREC_FP32:
+            return launch_tile<ATSNE_PREC_FP32>(c, b, p, w, st);
+        case ATSNE_PREC_BF16:
+            return launch_tile<ATSNE_PREC_BF16>(c, b, p, w, st);
+        default:
+            return launch_tile<ATSNE_PREC_FP8_E4M3>(c, b, p, w, st);
+    }
+}
+
+static SelArgs sel_args(const Corpus& c, const Batch& b, const SearchPlan& p, const SearchWs& w) {
+    SelArgs s;
+    s.X = c.X;
+    s.ld = c.ld;
+    s.D = c.D;
+    s.Dp = c.Dp;
+    s.norms = c.norms;
+    s.pmax = c.pmax;
+    s.M = b.M;
+    s.qids = b.qids;
+    s.m0 = b.m0;
+    s.nlims = b.nlims;
+    s.nlim = b.nlim;
+    s.key_lo = b.key_lo;
+    s.ks = b.ks;
+    s.k = b.k;
+    s.kcs = b.kcs;
+    s.kc = b.kc;
+    s.S = p.S;
+    s.cap = p.cap;
+    s.slots = w.slots;
+    s.counts = w.counts;
+    s.out_idx = b.out_idx;
+    s.out_d2 = b.out_d2;
+    s.out_flags = b.out_flags;
+    s.out_stride = b.out_stride;
+    s.scan_list = w.scan_list;
+    s.scan_count = w.misc + 1;
+    return s;
+}
+
+atsne_status knn_search(const Corpus& c, const Batch& b, const SearchPlan& p, void* ws, hipStream_t st) {
+    if (b.M == 0) return ATSNE_OK;
+    ATSNE_REQUIRE(b.M <= p.M && b.kc <= p.kc_max && b.k <= p.k_max, ATSNE_E_INVALID_ARG, "batch exceeds its plan");
+    const SearchWs w = carve(p, ws);
+    ATSNE_HIP(hipMemsetAsync(w.misc, 0, 256, st));
+    ATSNE_TRY(launch_tile_any(c, b, p, w, st));
+    const SelArgs s = sel_args(c, b, p, w);
+    {
+        ProfScope ps_("knn_select", st);
+        switch (c.prec) {
+            case ATSNE_PREC_FP32:
+                knn_select<ATSNE_PREC_FP32><<<dim3((unsigned)b.M), dim3(64), 0, st>>>(s);
+                break;
+            case ATSNE_PREC_BF16:
+                knn_select<ATSNE_PREC_BF16><<<dim3((unsigned)b.M), dim3(64), 0, st>>>(s);
+                break;
+            default:
+                knn_select<ATSNE_PREC_FP8_E4M3><<<dim3((unsigned)b.M), dim3(64), 0, st>>>(s);
+        }
+        ATSNE_LAUNCH_CHECK();
+    }
+    if (c.prec == ATSNE_PREC_FP32) {
+        const int grid = (int)std::min<int64_t>(b.M, 4 * (int64_t)device_cu_count());
+        ProfScope ps_("knn_scan", st);
+        knn_scan<<<dim3((unsigned)grid), dim3(256), 0, st>>>(s, 32, w.misc + 2);
+        ATSNE_LAUNCH_CHECK();
+    }
+    return ATSNE_OK;
+}
+
+atsne_status knn_reverse(const Corpus& c, const Batch& b, const SearchPlan& p, int32_t* res_idx, float* res_d2,
+                         uint8_t* res_flags, int64_t res_stride, int32_t* changed, int32_t* n_changed, void* ws,
+                         hipStream_t st) {
+    if (b.M == 0) return ATSNE_OK;
+    ATSNE_REQUIRE(c.prec == ATSNE_PREC_FP32, ATSNE_E_UNSUPPORTED, "reverse merge needs the FP32 corpus");
+    ATSNE_REQUIRE(b.tau0 && b.M <= p.M && b.kc <= p.kc_max, ATSNE_E_INVALID_ARG, "bad reverse batch");
+    const SearchWs w = carve(p, ws);
+    ATSNE_TRY(launch_tile_any(c, b, p, w, st));
+    RevArgs r;
+    r.s = sel_args(c, b, p, w);
+    r.res_idx = res_idx;
+    r.res_d2 = res_d2;
+    r.res_flags = res_flags;
+    r.res_stride = res_stride;
+    r.changed = changed;
+    r.n_changed = n_changed;
+    ProfScope ps_("knn_reverse_merge", st);
+    knn_reverse_merge<<<dim3((unsigned)b.M), dim3(64), 0, st>>>(r);
+    ATSNE_LAUNCH_CHECK();
+    return ATSNE_OK;
+}
+
+// ---- C ABI: standalone search over a caller corpus ----
+struct KnnPlan {
+    int prec, k, kc;
+    int64_t N, M, Mb;
+    int32_t D;
+    size_t b_corpus;
+    SearchPlan sp;
+    size_t total;
+};
+
 static atsne_status make_plan(int64_t N, int64_t M, int32_t D, int prec, int k, int k_cand, KnnPlan& p) {
     ATSNE_REQUIRE(prec == ATSNE_PREC_FP32 || prec == ATSNE_PREC_BF16 || prec == ATSNE_PREC_FP8_E4M3,
                   ATSNE_E_INVALID_ARG, "unknown precision %d", prec);
@@ -727,106 +1142,25 @@ static atsne_status make_plan(int64_t N, int64_t M, int32_t D, int prec, int k, 
     ATSNE_REQUIRE(M >= 0 && M < (1ll << 31), ATSNE_E_INVALID_ARG, "M=%lld out of range", (long long)M);
     ATSNE_REQUIRE(D >= 1 && D <= 65536, ATSNE_E_INVALID_ARG, "D=%d out of range", D);
     ATSNE_REQUIRE(k >= 1 && k <= N - 1, ATSNE_E_K_RANGE, "k=%d must be in [1, N-1=%lld]", k, (long long)(N - 1));
+    ATSNE_REQUIRE(k <= 1000, ATSNE_E_K_RANGE, "k=%d above the supported maximum 1000", k);
     int kc = k_cand > 0 ? k_cand : default_kcand(prec, k);
     kc = (int)std::min<int64_t>(kc, N - 1);
     ATSNE_REQUIRE(kc >= k && kc <= MAX_KC, ATSNE_E_K_RANGE, "k_cand=%d must be in [k=%d, %d]", kc, k, MAX_KC);
-    ATSNE_REQUIRE(k <= 1000, ATSNE_E_K_RANGE, "k=%d above the supported maximum 1000", k);
     p.prec = prec;
+    p.k = k;
+    p.kc = kc;
     p.N = N;
     p.M = M;
     p.D = D;
-    p.k = k;
-    p.kc = kc;
-    const int ce = chunk_elems(prec);
-    p.Dp = (int32_t)(ceil_div(D, ce) * ce);
-    p.n_chunks = p.Dp / ce;
-    p.N_pad = ceil_div(N, KT) * KT;
-    p.total_tiles = (int)(p.N_pad / KT);
-    p.cap = (int)align_up((size_t)(kc + KT + std::max(kc, 128)), 64);
+    p.b_corpus = corpus_bytes(prec, N, D);
     // Batch the queries so the candidate slots stay within ~2 GiB.
-    const int cu = device_cu_count();
-    const int slots_avail = cu;  // one 256-thread tile workgroup per CU
-    int64_t MBall = ceil_div(std::max<int64_t>(M, 1), QB);
-    int S = pick_splits(MBall, p.total_tiles, slots_avail);
-    const size_t slot_bytes = (size_t)p.cap * 8;
-    int64_t max_rows = (int64_t)((size_t)2 << 30) / (slot_bytes * S);
+    SearchPlan full = plan_search(std::max<int64_t>(M, 1), 0, N, k, kc);
+    const size_t per_row = (size_t)full.S * full.cap * 8;
+    int64_t max_rows = (int64_t)(((size_t)2 << 30) / per_row);
     max_rows = std::max<int64_t>(QB, max_rows / QB * QB);
     p.Mb = std::min<int64_t>(std::max<int64_t>(M, 1), max_rows);
-    p.MB = (int)ceil_div(p.Mb, QB);
-    if (p.Mb < M) S = pick_splits(p.MB, p.total_tiles, slots_avail);
-    p.S = S;
-    p.tiles_per_split = (int)ceil_div(p.total_tiles, S);
-    p.S = (int)ceil_div(p.total_tiles, p.tiles_per_split);
-    p.b_xp = (size_t)p.N_pad * p.Dp * elem_bytes(prec);
-    p.b_norm = (size_t)p.N_pad * 4;
-    p.b_scale = (size_t)p.N_pad * 4;
-    p.b_misc = 256;
-    p.b_slots = (size_t)p.MB * QB * p.S * slot_bytes;
-    p.b_counts = (size_t)p.MB * QB * p.S * 4;
-    p.b_list = (size_t)std::max<int64_t>(M, 1) * 4;
-    Arena a;
-    a.take<char>(p.b_xp);
-    a.take<char>(p.b_norm);
-    a.take<char>(p.b_scale);
-    a.take<char>(p.b_misc);
-    a.take<char>(p.b_slots);
-    a.take<char>(p.b_counts);
-    a.take<char>(p.b_list);
-    p.total = a.used;
-    return ATSNE_OK;
-}
-
-template <int P>
-static atsne_status run_knn(const KnnPlan& p, const float* X, int64_t ld, const int32_t* qids, int32_t* nbr_idx,
-                            float* nbr_d2, uint8_t* flags, void* wsp, hipStream_t st) {
-    Arena a(wsp, p.total);
-    void* Xp = a.take<char>(p.b_xp);
-    float* norms = a.take<float>(p.N_pad);
-    float* scales = a.take<float>(p.N_pad);
-    int32_t* misc = a.take<int32_t>(64);
-    uint64_t* slots = reinterpret_cast<uint64_t*>(a.take<char>(p.b_slots));
-    int32_t* counts = a.take<int32_t>((size_t)p.MB * QB * p.S);
-    int32_t* scan_list = a.take<int32_t>(std::max<int64_t>(p.M, 1));
-    uint32_t* nmax_bits = reinterpret_cast<uint32_t*>(misc);
-    int32_t* scan_count = misc + 1;
-    int32_t* cursor = misc + 2;
-
-    ATSNE_HIP(hipMemsetAsync(misc, 0, 256, st));
-    {
-        ProfScope ps_("knn_prep", st);
-        knn_prep<P><<<dim3((unsigned)ceil_div(p.N_pad, 4)), dim3(256), 0, st>>>(
-            X, p.N, p.D, ld, p.N_pad, p.Dp, Xp, norms, scales, nmax_bits);
-        ATSNE_LAUNCH_CHECK();
-    }
-    const int64_t row_units = (int64_t)p.Dp * elem_bytes(P) / 16;
-    for (int64_t m0 = 0; m0 < p.M; m0 += p.Mb) {
-        const int64_t Mb = std::min<int64_t>(p.Mb, p.M - m0);
-        const int MB = (int)ceil_div(Mb, QB);
-        {
-        ProfScope ps_("knn_tile", st);
-        knn_tile<P><<<dim3((unsigned)(MB * p.S)), dim3(TILE_THREADS), 0, st>>>(
-            reinterpret_cast<const uint4*>(Xp), row_units, p.n_chunks, norms, scales, p.N, qids, m0, Mb, MB, p.S,
-            p.tiles_per_split, p.total_tiles, p.kc, p.cap, slots, counts);
-        ATSNE_LAUNCH_CHECK();
-        }
-        {
-        ProfScope ps_("knn_select", st);
-        knn_select<P><<<dim3((unsigned)Mb), dim3(64), 0, st>>>(
-            X, ld, p.D, p.N, qids, m0, Mb, p.S, p.cap, p.kc, p.k, slots, counts, norms, nmax_bits, p.Dp,
-            nbr_idx + m0 * p.k, nbr_d2 + m0 * p.k, flags ? flags + m0 : nullptr, scan_list, scan_count);
-        ATSNE_LAUNCH_CHECK();
-        }
-        if (P == ATSNE_PREC_FP32) {
-            const int grid = (int)std::min<int64_t>(Mb, 4 * (int64_t)device_cu_count());
-            ProfScope ps_("knn_scan", st);
-            knn_scan<<<dim3((unsigned)grid), dim3(256), 0, st>>>(X, ld, p.D, p.N, qids, m0, p.k,
-                                                                  std::min(p.k + 32, SCAN_REGION - 24), scan_list,
-                                                                  scan_count, cursor, nbr_idx + m0 * p.k,
-                                                                  nbr_d2 + m0 * p.k, flags ? flags + m0 : nullptr);
-            ATSNE_LAUNCH_CHECK();
-            if (m0 + p.Mb < p.M) ATSNE_HIP(hipMemsetAsync(misc + 1, 0, 8, st));
-        }
-    }
+    p.sp = p.Mb < std::max<int64_t>(M, 1) ? plan_search(p.Mb, 0, N, k, kc) : full;
+    p.total = align_up(p.b_corpus, 256) + p.sp.ws_bytes;
     return ATSNE_OK;
 }
 
@@ -842,15 +1176,26 @@ static atsne_status knn_impl(const float* X, int64_t N, int32_t D, int64_t ld, c
     hipStream_t st = static_cast<hipStream_t>(stream);
     Scratch scr;
     ATSNE_TRY(scr.acquire(ws, ws_bytes, p.total, st));
-    switch (prec) {
-        case ATSNE_PREC_FP32:
-            return run_knn<ATSNE_PREC_FP32>(p, X, ld, qids, nbr_idx, nbr_d2, flags, scr.ptr, st);
-        case ATSNE_PREC_BF16:
-            return run_knn<ATSNE_PREC_BF16>(p, X, ld, qids, nbr_idx, nbr_d2, flags, scr.ptr, st);
-        case ATSNE_PREC_FP8_E4M3:
-            return run_knn<ATSNE_PREC_FP8_E4M3>(p, X, ld, qids, nbr_idx, nbr_d2, flags, scr.ptr, st);
+    Corpus c;
+    corpus_bind(c, (int)prec, X, ld, D, N, scr.ptr);
+    ATSNE_TRY(corpus_prep(c, 0, c.rows_cap, N, st));
+    void* sws = static_cast<char*>(scr.ptr) + align_up(p.b_corpus, 256);
+    for (int64_t m0 = 0; m0 < M; m0 += p.Mb) {
+        Batch b;
+        b.M = std::min<int64_t>(p.Mb, M - m0);
+        b.qids = qids ? qids + m0 : nullptr;
+        b.m0 = m0;
+        b.nlim = N;
+        b.key_lo = 0;
+        b.k = k;
+        b.kc = p.kc;
+        b.out_idx = nbr_idx + m0 * k;
+        b.out_d2 = nbr_d2 + m0 * k;
+        b.out_flags = flags ? flags + m0 : nullptr;
+        b.out_stride = k;
+        ATSNE_TRY(knn_search(c, b, p.sp, sws, st));
     }
-    return ATSNE_E_INVALID_ARG;
+    return ATSNE_OK;
 }
 
 }  // namespace atsne

@@ -1,0 +1,86 @@
+// Internal C++ interface of the kNN search, shared by the C ABI entry points
+// (knn.hip) and the serving loop (serve.cpp).  Not part of the public ABI.
+#pragma once
+
+#include "common.h"
+
+namespace atsne {
+
+constexpr int KNN_KT = 256;  // keys per tile; corpus rows are padded to a multiple
+
+// A device-resident corpus prepared for the contraction: padded copy in the
+// contraction's element type, row norms, per-row scales (FP8) and the prefix
+// maximum of the norms (pmax[i] = max_{j <= i} n_j, used by the error bound).
+struct Corpus {
+    int prec = ATSNE_PREC_FP32;
+    const float* X = nullptr;  // FP32 source rows (re-rank reads these)
+    int64_t ld = 0;
+    int32_t D = 0, Dp = 0;
+    int n_chunks = 0;
+    int64_t row_units = 0;  // 16-byte units per padded row
+    int64_t rows_cap = 0;   // padded row capacity (multiple of KNN_KT)
+    void* Xp = nullptr;
+    float* norms = nullptr;
+    float* scales = nullptr;
+    float* pmax = nullptr;
+};
+
+size_t corpus_bytes(int prec, int64_t rows_cap, int32_t D);
+// Carve the corpus buffers out of `mem` (corpus_bytes bytes, 256-aligned).
+void corpus_bind(Corpus& c, int prec, const float* X, int64_t ld, int32_t D, int64_t rows_cap, void* mem);
+// Prepare rows [r0, r1) (r1 <= rows_cap; rows >= n_live are zero padding).
+// pmax is extended from pmax[r0 - 1], so earlier rows must be prepared.
+atsne_status corpus_prep(const Corpus& c, int64_t r0, int64_t r1, int64_t n_live, hipStream_t st);
+
+// One launch worth of query rows.  Per-row arrays are device pointers; a
+// null pointer selects the uniform value next to it.
+struct Batch {
+    int64_t M = 0;
+    const int32_t* qids = nullptr;  // corpus id of row m (also its self id); null: m0 + m
+    int64_t m0 = 0;
+    const int32_t* nlims = nullptr;  // keys valid below nlims[m]; null: nlim
+    int64_t nlim = 0;
+    int64_t key_lo = 0;  // keys valid at or above key_lo
+    const int32_t* ks = nullptr;
+    int k = 0;
+    const int32_t* kcs = nullptr;
+    int kc = 0;
+    const float* tau0 = nullptr;  // reverse mode: per-row distance that candidates must beat
+    int64_t tau0_stride = 0;      // element stride of tau0 (rows' d_max inside a neighbour table)
+    int32_t* out_idx = nullptr;
+    float* out_d2 = nullptr;
+    uint8_t* out_flags = nullptr;
+    int64_t out_stride = 0;
+};
+
+struct SearchPlan {
+    int MB = 0, S = 1, tiles_per_split = 1, tile_lo = 0, tile_hi = 0, cap = 0, kc_max = 0, k_max = 0;
+    int64_t M = 0;
+    size_t ws_bytes = 0;
+};
+
+// Plan a search of M rows over keys [key_lo, key_hi) with at most kc_max
+// candidates and k_max neighbours per row.
+// s_max > 0 caps the number of key splits (to fit a fixed workspace).
+SearchPlan plan_search(int64_t M, int64_t key_lo, int64_t key_hi, int k_max, int kc_max, int s_max = 0);
+
+// Forward search: exact k nearest neighbours of every batch row (candidate
+// contraction, FP32 re-rank, certificate + exact scan on the FP32 path).
+atsne_status knn_search(const Corpus& c, const Batch& b, const SearchPlan& p, void* ws, hipStream_t st);
+
+// Reverse merge (Eq. 13): batch rows are resident rows whose neighbour lists
+// live in (res_idx, res_d2) with stride res_stride and k = b.k; keys are the
+// newly inserted rows [key_lo, key_hi).  Every new row strictly closer than a
+// resident row's farthest neighbour enters its list, evicting the farthest;
+// ids of changed rows are appended to changed[*n_changed].
+atsne_status knn_reverse(const Corpus& c, const Batch& b, const SearchPlan& p, int32_t* res_idx, float* res_d2,
+                         uint8_t* res_flags, int64_t res_stride, int32_t* changed, int32_t* n_changed, void* ws,
+                         hipStream_t st);
+
+// Calibrate rows of a neighbour table in place: row r is table row
+// (row_ids ? row_ids[r] : r); d2/P rows have stride `stride`, k entries.
+atsne_status calibrate_table(const float* d2, int64_t stride, const int32_t* row_ids, const int32_t* n_rows_dev,
+                             int64_t n_rows, int k, float mu, float tol, int max_iter, float* P, float* beta,
+                             float* perp, uint8_t* flags, hipStream_t st);
+
+}  // namespace atsne
