@@ -33,6 +33,12 @@ def parse():
     ap.add_argument("--workload", default="imagelike", choices=["imagelike", "mixture"])
     ap.add_argument("--no-bf16", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--profile-kernel", default=None, choices=["fp32", "bf16", "fp8"],
+                    help="profiling mode: one warm-up and one timed kNN at this precision, then a 1 GiB device "
+                         "copy (the reference kernel for scaling HBM byte counters); prints the launch shapes")
+    ap.add_argument("--serve-rate", type=float, default=25.0, help="Poisson request rate (req/s)")
+    ap.add_argument("--serve-requests", type=int, default=120)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
     return ap.parse_args()
 
@@ -66,6 +72,80 @@ def run_path(A, torch, Xt, mu, k, prec, steps, warmup):
     A.profile_enable(False)
     flags = fl.cpu().numpy()
     return dict(wall=wall, stages=stages, idx=idx, P=P, val=val, flags=flags)
+
+
+def serve_load(A, torch, X, rate, n_req, n_warm, seed=5):
+    """Poisson stream against a server holding X: half inserts of 64-4096 new
+    points (same generator, fresh noise), half refines of 1000-20000 resident
+    ids at perplexity 10, 30 or 50.  Latency = completion - submission."""
+    import threading
+
+    from paper_1512_01655_amd import datagen
+
+    rng = np.random.default_rng(seed)
+    kinds = rng.random(n_req) < 0.5
+    sizes = np.where(kinds, rng.integers(64, 4097, n_req), rng.integers(1000, 20001, n_req))
+    mus = rng.choice([10.0, 30.0, 50.0], n_req)
+    gaps = rng.exponential(1.0 / rate, n_req)
+    n_new = int(sizes[kinds].sum())
+    pool = torch.from_numpy(datagen.image_like(n=max(n_new, 1), noise_seed=seed + 1000)).cuda()
+    srv = A.Server(torch.from_numpy(X).cuda(), 30.0, capacity_rows=X.shape[0] + n_new + 1)
+    rids, lat, rows = [], [], []
+    done = threading.Event()
+
+    def collect():
+        i = 0
+        while i < n_req:
+            while i >= len(rids):
+                time.sleep(0.0005)
+            r = srv.wait(rids[i], fetch=False)
+            if r["status"] != 0:
+                raise RuntimeError("request failed: %s" % r)
+            lat.append(r["t_complete_ms"] - r["t_submit_ms"])
+            rows.append(r["n_rows"])
+            srv.release(rids[i])
+            i += 1
+        done.set()
+
+    th = threading.Thread(target=collect)
+    th.start()
+    off = 0
+    corpus_n = X.shape[0]
+    t_start = time.perf_counter()
+    t_next = t_start
+    t_first = None
+    for i in range(n_req):
+        t_next += gaps[i]
+        while time.perf_counter() < t_next:
+            time.sleep(0.0002)
+        if i == n_warm:
+            t_first = time.perf_counter()
+        if kinds[i]:
+            B = int(sizes[i])
+            rids.append(srv.insert(pool[off:off + B]))
+            off += B
+            corpus_n += B
+        else:
+            ids = rng.choice(corpus_n, size=int(sizes[i]), replace=False).astype(np.int32)
+            rids.append(srv.refine(ids, float(mus[i])))
+    done.wait()
+    th.join()
+    t_end = time.perf_counter()
+    st = srv.stats()
+    srv.close()
+    lat_m = np.array(lat[n_warm:])
+    rows_m = np.array(rows[n_warm:])
+    span = t_end - t_first
+    return {
+        "rate_req_s": rate, "requests": n_req - n_warm, "warmup_requests": n_warm,
+        "p50_ms": round(float(np.percentile(lat_m, 50)), 2), "p99_ms": round(float(np.percentile(lat_m, 99)), 2),
+        "mean_ms": round(float(lat_m.mean()), 2), "throughput_req_s": round((n_req - n_warm) / span, 2),
+        "rows_per_s": round(float(rows_m.sum()) / span, 1),
+        "mix": "0.5 insert (64-4096 points) / 0.5 refine (1000-20000 ids, mu in {10,30,50})",
+        "corpus_rows_start": int(X.shape[0]), "corpus_rows_end": int(st["corpus_rows"]),
+        "launches": int(st["launches"]), "max_requests_per_launch": int(st["max_requests_per_launch"]),
+        "max_concurrent": int(st["max_concurrent"]),
+    }
 
 
 def cpu_baseline(X, mu, k, target_s):
@@ -112,6 +192,16 @@ def main():
     N, D = X.shape
     Xt = torch.from_numpy(X).cuda()
     log("bench: %s on %s" % (name, torch.cuda.get_device_name(0)))
+    if a.profile_kernel:
+        for _ in range(2):
+            idx, d2, fl = A.knn(Xt, k, prec=a.profile_kernel)
+            torch.cuda.synchronize()
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = src.clone()
+        torch.cuda.synchronize()
+        log("profile: knn %s N=%d D=%d k=%d; copy kernel moved %d bytes read + %d bytes written" % (
+            a.profile_kernel, N, D, k, src.numel() * 4, dst.numel() * 4))
+        return
 
     r = run_path(A, torch, Xt, mu, k, "fp32", a.steps, a.warmup)
     ms_step = 1e3 * r["wall"] / a.steps
@@ -126,7 +216,7 @@ def main():
     stages_ms = {kname: round(v[0] / a.steps, 3) for kname, v in r["stages"].items()}
     log("fp32: %.1f points/s, %.2f ms/step, stages %s" % (value, ms_step, stages_ms))
     line = {
-        "metric": "kNN+P points/s at N=70k,D=784 (FP32 vs BF16+rerank)",
+        "metric": "kNN+P points/s at N=70k,D=784 (FP32 vs BF16+rerank); serve p50/p99 ms",
         "value": round(value, 1), "unit": "points/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
@@ -155,6 +245,10 @@ def main():
             "agree_with_fp32_rows": float((rb["idx"] == r["idx"]).all(1).float().mean().item()),
         }
         log("bf16: %.1f points/s (x%.2f)" % (vb, vb / value))
+    if not a.no_serve and a.workload == "imagelike":
+        log("serve: Poisson stream at %.0f req/s ..." % a.serve_rate)
+        line["serve"] = serve_load(A, torch, X, a.serve_rate, a.serve_requests + 10, 10)
+        log("serve: p50 %.1f ms, p99 %.1f ms" % (line["serve"]["p50_ms"], line["serve"]["p99_ms"]))
     if not a.no_cpu_baseline:
         log("cpu baseline: timing the FP64 oracle on a bounded sample ...")
         line["cpu_baseline"] = cpu_baseline(X, mu, k, a.cpu_seconds)

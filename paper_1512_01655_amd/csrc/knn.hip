@@ -24,6 +24,7 @@
 //   knn_scan       exact FP32 linear scan for the queued rows (rare).
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "knn_internal.h"
 #include "wave.h"
@@ -104,7 +105,15 @@ __global__ __launch_bounds__(256) void knn_prep(const float* __restrict__ X, int
         if (live)
             for (int d = l; d < D; d += WAVE) amax = fmaxf(amax, fabsf(x[d]));
         amax = wave_max(amax);
-        s = amax > 0.0f ? amax / 448.0f : 1.0f;
+        // smallest power of two s with amax / s <= 448: the MFMA applies it
+        // exactly through its E8M0 scale operand
+        s = 1.0f;
+        if (amax > 0.0f) {
+            int e;
+            frexpf(amax / 448.0f, &e);  // amax/448 = f 2^e, f in [0.5, 1)
+            s = ldexpf(1.0f, e);
+            if (ldexpf(1.0f, e - 1) >= amax / 448.0f) s = ldexpf(1.0f, e - 1);
+        }
     }
     float acc = 0.0f;
     for (int d = l; d < Dp; d += WAVE) {
@@ -187,36 +196,55 @@ __device__ __forceinline__ int chunk_unit(int l, int i) {
     return 2 * i + (l >> 5);
 }
 
-template <int P>
-__device__ __forceinline__ f32x16 mfma_chunk(f32x16 acc, const uint4 (&a)[4], const uint4 (&b)[4]) {
+// Two key blocks against one query block over one chunk, their MFMAs
+// interleaved so consecutive instructions use different accumulators.  For
+// FP8 the per-row power-of-two scales enter as E8M0 scale operands (sa0, sa1
+// for the key rows of each block, sb for the query column).
+template <int P, bool FIRST>
+__device__ __forceinline__ void mfma_pair(f32x16& acc0, f32x16& acc1, const uint4 (&a0)[4], const uint4 (&a1)[4],
+                                          const uint4 (&b)[4], int sa0, int sa1, int sb) {
+    const f32x16 zero = {};
+    f32x16 c0 = FIRST ? zero : acc0;
+    f32x16 c1 = FIRST ? zero : acc1;
     if constexpr (P == ATSNE_PREC_FP32) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a[i].x), __uint_as_float(b[i].x), acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a[i].y), __uint_as_float(b[i].y), acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a[i].z), __uint_as_float(b[i].z), acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a[i].w), __uint_as_float(b[i].w), acc, 0, 0, 0);
+            c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a0[i].x), __uint_as_float(b[i].x), c0, 0, 0, 0);
+            c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a1[i].x), __uint_as_float(b[i].x), c1, 0, 0, 0);
+            c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a0[i].y), __uint_as_float(b[i].y), c0, 0, 0, 0);
+            c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a1[i].y), __uint_as_float(b[i].y), c1, 0, 0, 0);
+            c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a0[i].z), __uint_as_float(b[i].z), c0, 0, 0, 0);
+            c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a1[i].z), __uint_as_float(b[i].z), c1, 0, 0, 0);
+            c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a0[i].w), __uint_as_float(b[i].w), c0, 0, 0, 0);
+            c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a1[i].w), __uint_as_float(b[i].w), c1, 0, 0, 0);
         }
     } else if constexpr (P == ATSNE_PREC_BF16) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            bf16x8 va = __builtin_bit_cast(bf16x8, a[i]);
-            bf16x8 vb = __builtin_bit_cast(bf16x8, b[i]);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(va, vb, acc, 0, 0, 0);
+            const bf16x8 vb = __builtin_bit_cast(bf16x8, b[i]);
+            c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a0[i]), vb, c0, 0, 0, 0);
+            c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a1[i]), vb, c1, 0, 0, 0);
         }
     } else {
 #pragma unroll
         for (int i = 0; i < 4; i += 2) {
-            i32x8 va = {(int)a[i].x, (int)a[i].y, (int)a[i].z, (int)a[i].w,
-                        (int)a[i + 1].x, (int)a[i + 1].y, (int)a[i + 1].z, (int)a[i + 1].w};
-            i32x8 vb = {(int)b[i].x, (int)b[i].y, (int)b[i].z, (int)b[i].w,
-                        (int)b[i + 1].x, (int)b[i + 1].y, (int)b[i + 1].z, (int)b[i + 1].w};
-            // format 0 = FP8 E4M3 for both operands; E8M0 scale 127 = 2^0
-            acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(va, vb, acc, 0, 0, 0, 127, 0, 127);
+            const i32x8 vb = {(int)b[i].x, (int)b[i].y, (int)b[i].z, (int)b[i].w,
+                              (int)b[i + 1].x, (int)b[i + 1].y, (int)b[i + 1].z, (int)b[i + 1].w};
+            const i32x8 va0 = {(int)a0[i].x, (int)a0[i].y, (int)a0[i].z, (int)a0[i].w,
+                               (int)a0[i + 1].x, (int)a0[i + 1].y, (int)a0[i + 1].z, (int)a0[i + 1].w};
+            const i32x8 va1 = {(int)a1[i].x, (int)a1[i].y, (int)a1[i].z, (int)a1[i].w,
+                               (int)a1[i + 1].x, (int)a1[i + 1].y, (int)a1[i + 1].z, (int)a1[i + 1].w};
+            // operand format 0 = FP8 E4M3 for A and B
+            c0 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(va0, vb, c0, 0, 0, 0, sa0, 0, sb);
+            c1 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(va1, vb, c1, 0, 0, 0, sa1, 0, sb);
         }
     }
-    return acc;
+    acc0 = c0;
+    acc1 = c1;
 }
+
+// E8M0 encoding of a power-of-two float scale: its biased exponent.
+__device__ __forceinline__ int e8m0_of(float s) { return (int)((__float_as_uint(s) >> 23) & 0xffu); }
 
 // Shrink one candidate slot to its best `kc` keys (wave-wide). Returns the
 // key of rank kc, which becomes the slot's threshold.
@@ -271,10 +299,14 @@ struct TileArgs {
 
 template <int P>
 __global__ __launch_bounds__(TILE_THREADS) __attribute__((amdgpu_waves_per_eu(1, 1))) void knn_tile(TileArgs a) {
-    __shared__ uint4 Ks[KT * ROW_UNITS];
-    __shared__ uint4 Qs[QB * ROW_UNITS];
-    __shared__ float Kn[KT];
-    __shared__ float Ksc[KT];
+    // double-buffered tiles: one barrier per chunk, the next chunk's global
+    // loads in flight while this chunk's MFMAs run
+    __shared__ uint4 Ks[2][KT * ROW_UNITS];
+    __shared__ uint4 Qs[2][QB * ROW_UNITS];
+    // per-tile norms/scales: three buffers, because a tile's epilogue runs
+    // after the barrier that lets faster waves stage the following tiles
+    __shared__ float Kn[3][KT];
+    __shared__ float Ksc[3][KT];
     __shared__ uint32_t hist_all[4][256];
 
     const int t = threadIdx.x;
@@ -286,16 +318,15 @@ __global__ __launch_bounds__(TILE_THREADS) __attribute__((amdgpu_waves_per_eu(1,
     const int tile_end = min(a.tile_hi, tile_begin + a.tiles_per_split);
     uint32_t* hist = hist_all[w];
     const int64_t row_units = a.row_units;
+    const int n_chunks = a.n_chunks;
 
     // Rows of the query tile this thread loads (4 rows, unit t & 7).
-    int64_t qrow_off[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        int r = (t >> 3) + 32 * i;
-        int64_t m = (int64_t)qb * QB + r;
-        int64_t row = m < a.M ? load_qid(a.qids, a.m0, m) : 0;
-        qrow_off[i] = row * row_units + (t & 7);
-    }
+    auto qrow_of = [&](int i) {
+        const int64_t m = (int64_t)qb * QB + (t >> 3) + 32 * i;
+        const int64_t row = m < a.M ? load_qid(a.qids, a.m0, m) : 0;
+        return row * row_units + (t & 7);
+    };
+    const int64_t qoff0 = qrow_of(0), qoff1 = qrow_of(1), qoff2 = qrow_of(2), qoff3 = qrow_of(3);
 
     // Per-lane query state (lanes l and l+32 share query 32w + l%32).
     const int qloc = 32 * w + (l & 31);
@@ -304,7 +335,7 @@ __global__ __launch_bounds__(TILE_THREADS) __attribute__((amdgpu_waves_per_eu(1,
     const int64_t self = qvalid ? load_qid(a.qids, a.m0, mq) : -1;
     const int64_t nl = qvalid ? (a.nlims ? (int64_t)a.nlims[mq] : a.nlim) : 0;
     const int kcq = qvalid ? (a.kcs ? a.kcs[mq] : a.kc) : 0;
-    const float qscale = (P == ATSNE_PREC_FP8_E4M3 && qvalid) ? a.scales[self] : 1.0f;
+    const int sq_e8 = (P == ATSNE_PREC_FP8_E4M3 && qvalid) ? e8m0_of(a.scales[self]) : 127;
     uint64_t* myslot = a.slots + ((size_t)(qvalid ? mq : 0) * a.S + split) * (size_t)a.cap;
     float tau = -INFINITY;
     if (qvalid) {
@@ -318,55 +349,94 @@ __global__ __launch_bounds__(TILE_THREADS) __attribute__((amdgpu_waves_per_eu(1,
             tau = dmax - nq + fp32_contraction_bound(a.Dp, nq, nmax, dmax) * 2.0f + 1e-30f;
         }
     }
+    // smallest key bound of the wave's queries: tiles below it need no range checks
+    int nl_min = qvalid ? (int)nl : 0x7fffffff;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) nl_min = min(nl_min, __shfl_xor(nl_min, o, WAVE));
     int count = 0;
 
-    uint4 pk[8], pq[4];
-    auto load_chunk = [&](int tile, int c) {
-        const uint4* kbase = a.Xp + (int64_t)tile * KT * row_units + (int64_t)c * CHUNK_UNITS;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) pk[i] = kbase[(int64_t)((t >> 3) + 32 * i) * row_units + (t & 7)];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) pq[i] = a.Xp[qrow_off[i] + (int64_t)c * CHUNK_UNITS];
-    };
+    // Global -> register staging of one chunk (8 key units + 4 query units per
+    // thread) and register -> LDS parking.  Written as macros over plain
+    // locals so the staging stays in registers.
+    uint4 pk0, pk1, pk2, pk3, pk4, pk5, pk6, pk7, pq0, pq1, pq2, pq3;
+    const int64_t krow_ = (int64_t)(t >> 3) * row_units + (t & 7);
+    const int64_t kstep_ = 32 * row_units;
+#define ATSNE_LOAD_CHUNK(TILE, C)                                                                    \
+    do {                                                                                             \
+        const uint4* kb_ = a.Xp + (int64_t)(TILE) * KT * row_units + (int64_t)(C) * CHUNK_UNITS + krow_; \
+        pk0 = kb_[0];                                                                                \
+        pk1 = kb_[kstep_];                                                                           \
+        pk2 = kb_[2 * kstep_];                                                                       \
+        pk3 = kb_[3 * kstep_];                                                                       \
+        pk4 = kb_[4 * kstep_];                                                                       \
+        pk5 = kb_[5 * kstep_];                                                                       \
+        pk6 = kb_[6 * kstep_];                                                                       \
+        pk7 = kb_[7 * kstep_];                                                                       \
+        const int64_t co_ = (int64_t)(C) * CHUNK_UNITS;                                              \
+        pq0 = a.Xp[qoff0 + co_];                                                                     \
+        pq1 = a.Xp[qoff1 + co_];                                                                     \
+        pq2 = a.Xp[qoff2 + co_];                                                                     \
+        pq3 = a.Xp[qoff3 + co_];                                                                     \
+    } while (0)
+#define ATSNE_STORE_CHUNK(BUF, TILE, C)                                                              \
+    do {                                                                                             \
+        uint4* ks_ = &Ks[BUF][(t >> 3) * ROW_UNITS + (t & 7)];                                      \
+        ks_[0] = pk0;                                                                                \
+        ks_[32 * ROW_UNITS] = pk1;                                                                   \
+        ks_[64 * ROW_UNITS] = pk2;                                                                   \
+        ks_[96 * ROW_UNITS] = pk3;                                                                   \
+        ks_[128 * ROW_UNITS] = pk4;                                                                  \
+        ks_[160 * ROW_UNITS] = pk5;                                                                  \
+        ks_[192 * ROW_UNITS] = pk6;                                                                  \
+        ks_[224 * ROW_UNITS] = pk7;                                                                  \
+        uint4* qs_ = &Qs[BUF][(t >> 3) * ROW_UNITS + (t & 7)];                                      \
+        qs_[0] = pq0;                                                                                \
+        qs_[32 * ROW_UNITS] = pq1;                                                                   \
+        qs_[64 * ROW_UNITS] = pq2;                                                                   \
+        qs_[96 * ROW_UNITS] = pq3;                                                                   \
+        if ((C) == 0) {                                                                              \
+            Kn[(TILE) % 3][t] = a.norms[(int64_t)(TILE) * KT + t];                                  \
+            if (P == ATSNE_PREC_FP8_E4M3) Ksc[(TILE) % 3][t] = a.scales[(int64_t)(TILE) * KT + t];  \
+        }                                                                                            \
+    } while (0)
 
-    const int n_chunks = a.n_chunks;
-    if (tile_begin < tile_end) load_chunk(tile_begin, 0);
-    for (int tile = tile_begin; tile < tile_end; ++tile) {
-        f32x16 acc[NKB];
+    f32x16 acc[NKB];
+    int ksc_e8[NKB];
+    // One chunk of the contraction from LDS buffer `buf`: key blocks in pairs,
+    // the next pair's fragments read while the current pair's MFMAs run.
+    auto compute = [&](int buf, auto first_tag) __attribute__((always_inline)) {
+        constexpr bool FIRST = decltype(first_tag)::value;
+        const uint4* K = Ks[buf];
+        uint4 bq[4], ca0[4], ca1[4], na0[4], na1[4];
 #pragma unroll
-        for (int b = 0; b < NKB; ++b)
+        for (int i = 0; i < 4; ++i) bq[i] = Qs[buf][qloc * ROW_UNITS + chunk_unit<P>(l, i)];
 #pragma unroll
-            for (int r = 0; r < 16; ++r) acc[b][r] = 0.0f;
-
-        for (int c = 0; c < n_chunks; ++c) {
-            __syncthreads();
+        for (int i = 0; i < 4; ++i) {
+            ca0[i] = K[(0 + (l & 31)) * ROW_UNITS + chunk_unit<P>(l, i)];
+            ca1[i] = K[(32 + (l & 31)) * ROW_UNITS + chunk_unit<P>(l, i)];
+        }
 #pragma unroll
-            for (int i = 0; i < 8; ++i) Ks[((t >> 3) + 32 * i) * ROW_UNITS + (t & 7)] = pk[i];
+        for (int pr = 0; pr < NKB / 2; ++pr) {
+            if (pr + 1 < NKB / 2) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) Qs[((t >> 3) + 32 * i) * ROW_UNITS + (t & 7)] = pq[i];
-            if (c == 0) {
-                Kn[t] = a.norms[(int64_t)tile * KT + t];
-                if (P == ATSNE_PREC_FP8_E4M3) Ksc[t] = a.scales[(int64_t)tile * KT + t];
+                for (int i = 0; i < 4; ++i) {
+                    na0[i] = K[(64 * (pr + 1) + (l & 31)) * ROW_UNITS + chunk_unit<P>(l, i)];
+                    na1[i] = K[(64 * (pr + 1) + 32 + (l & 31)) * ROW_UNITS + chunk_unit<P>(l, i)];
+                }
             }
-            __syncthreads();
-            if (c + 1 < n_chunks)
-                load_chunk(tile, c + 1);
-            else if (tile + 1 < tile_end)
-                load_chunk(tile + 1, 0);
-
-            uint4 bq[4];
+            mfma_pair<P, FIRST>(acc[2 * pr], acc[2 * pr + 1], ca0, ca1, bq, ksc_e8[2 * pr], ksc_e8[2 * pr + 1], sq_e8);
+            if (pr + 1 < NKB / 2) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) bq[i] = Qs[qloc * ROW_UNITS + chunk_unit<P>(l, i)];
-#pragma unroll
-            for (int b = 0; b < NKB; ++b) {
-                uint4 ak[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) ak[i] = Ks[(32 * b + (l & 31)) * ROW_UNITS + chunk_unit<P>(l, i)];
-                acc[b] = mfma_chunk<P>(acc[b], ak, bq);
+                for (int i = 0; i < 4; ++i) {
+                    ca0[i] = na0[i];
+                    ca1[i] = na1[i];
+                }
             }
         }
+    };
 
-        // ---- epilogue: make room, then filter this tile's candidates ----
+    auto epilogue = [&](int tile) __attribute__((always_inline)) {
+        // make room, then filter this tile's candidates
         {
             uint64_t need = ballot(count > a.cap - KT) & 0xffffffffull;
             while (need) {
@@ -382,38 +452,74 @@ __global__ __launch_bounds__(TILE_THREADS) __attribute__((amdgpu_waves_per_eu(1,
                 }
             }
         }
-        const int64_t key0 = (int64_t)tile * KT;
+        const int key0 = tile * KT;
+        // tiles inside every query's key range skip the per-key range checks
+        const bool edge = key0 < a.key_lo || key0 + KT > nl_min;
+        const float* kn = Kn[tile % 3];
 #pragma unroll
         for (int b = 0; b < NKB; ++b) {
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
                 const int kl = 32 * b + 8 * g + 4 * (l >> 5);
-                float4 nj = *reinterpret_cast<const float4*>(&Kn[kl]);
-                float4 sj = make_float4(1.f, 1.f, 1.f, 1.f);
-                if (P == ATSNE_PREC_FP8_E4M3) sj = *reinterpret_cast<const float4*>(&Ksc[kl]);
+                const float4 nj = *reinterpret_cast<const float4*>(&kn[kl]);
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const int64_t key = key0 + kl + e;
                     const float nje = e == 0 ? nj.x : e == 1 ? nj.y : e == 2 ? nj.z : nj.w;
-                    float s = acc[b][4 * g + e];
-                    if (P == ATSNE_PREC_FP8_E4M3) {
-                        const float sje = e == 0 ? sj.x : e == 1 ? sj.y : e == 2 ? sj.z : sj.w;
-                        s *= qscale * sje;
-                    }
-                    const float d = fmaf(-2.0f, s, nje);
-                    const bool pass = (d < tau) && (key >= a.key_lo) && (key < nl) && (key != self);
-                    const uint64_t m = ballot(pass);
-                    if (m) {
+                    const float d = fmaf(-2.0f, acc[b][4 * g + e], nje);
+                    const int key = key0 + kl + e;
+                    bool pass = d < tau;
+                    if (edge) pass = pass && key >= a.key_lo && key < nl;
+                    if (ballot(pass)) {
+                        pass = pass && key != self;
+                        const uint64_t m = ballot(pass);
                         const uint32_t lo = (uint32_t)m, hi = (uint32_t)(m >> 32);
                         const int q = l & 31;
                         const int bl = (lo >> q) & 1, bh = (hi >> q) & 1;
                         const int pos = count + ((l >> 5) ? bl : 0);
-                        if (pass) myslot[pos] = pack_key(d, (int32_t)key);
+                        if (pass) myslot[pos] = pack_key(d, key);
                         count += bl + bh;
                     }
                 }
             }
         }
+    };
+
+    const int n_tiles = tile_end - tile_begin;
+    const int total_g = n_tiles * n_chunks;
+    if (total_g > 0) {
+        ATSNE_LOAD_CHUNK(tile_begin, 0);
+        ATSNE_STORE_CHUNK(0, tile_begin, 0);
+        if (total_g > 1) ATSNE_LOAD_CHUNK(tile_begin + (n_chunks > 1 ? 0 : 1), n_chunks > 1 ? 1 : 0);
+        __syncthreads();
+    }
+    int g = 0;
+    for (int tile = tile_begin; tile < tile_end; ++tile) {
+        if (P == ATSNE_PREC_FP8_E4M3) {
+#pragma unroll
+            for (int b = 0; b < NKB; ++b) ksc_e8[b] = e8m0_of(Ksc[tile % 3][32 * b + (l & 31)]);
+        } else {
+#pragma unroll
+            for (int b = 0; b < NKB; ++b) ksc_e8[b] = 127;
+        }
+        for (int c = 0; c < n_chunks; ++c, ++g) {
+            if (c == 0)
+                compute(g & 1, std::true_type{});
+            else
+                compute(g & 1, std::false_type{});
+            if (g + 1 < total_g) {
+                // regs hold chunk g+1; park it in the other buffer, fetch g+2
+                const int c1 = (c + 1 == n_chunks) ? 0 : c + 1;
+                const int t1 = (c + 1 == n_chunks) ? tile + 1 : tile;
+                ATSNE_STORE_CHUNK((g + 1) & 1, t1, c1);
+                if (g + 2 < total_g) {
+                    const int c2 = (c1 + 1 == n_chunks) ? 0 : c1 + 1;
+                    const int t2 = (c1 + 1 == n_chunks) ? t1 + 1 : t1;
+                    ATSNE_LOAD_CHUNK(t2, c2);
+                }
+            }
+            __syncthreads();
+        }
+        epilogue(tile);
     }
 
     // Final shrink so each slot hands at most kc candidates to the next stage.
@@ -430,6 +536,8 @@ __global__ __launch_bounds__(TILE_THREADS) __attribute__((amdgpu_waves_per_eu(1,
         }
     }
     if (qvalid && l < 32) a.counts[mq * a.S + split] = count;
+#undef ATSNE_LOAD_CHUNK
+#undef ATSNE_STORE_CHUNK
 }
 
 // ---------------------------------------------------------------------------
