@@ -35,12 +35,22 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 
-constexpr int QB = 128;         // queries per workgroup (4 waves x 32)
+// Workgroup geometry per contraction type: FP32 and BF16 run 8 waves (256
+// queries x 256 keys, two waves per SIMD so one wave's epilogue and LDS
+// waits hide behind the other's MFMAs); FP8 keeps 4 waves (128 x 256) at one
+// wave per SIMD, where its scaled MFMAs fit the 512-register budget.
+template <int P>
+struct TileGeom {
+    static constexpr int WAVES = P == ATSNE_PREC_FP8_E4M3 ? 4 : 8;
+    static constexpr int THREADS = 64 * WAVES;
+    static constexpr int QB = 32 * WAVES;  // queries per workgroup
+    static constexpr int WPE = P == ATSNE_PREC_FP8_E4M3 ? 1 : 2;
+};
+__host__ __device__ constexpr int qb_of(int prec) { return prec == ATSNE_PREC_FP8_E4M3 ? 128 : 256; }
 constexpr int KT = KNN_KT;      // keys per tile (8 MFMA blocks of 32)
 constexpr int NKB = KT / 32;    // key blocks per tile
 constexpr int CHUNK_UNITS = 8;  // 16-byte units per row per D-chunk (128 bytes)
 constexpr int ROW_UNITS = 9;    // LDS row stride in 16-byte units (one unit of padding)
-constexpr int TILE_THREADS = 256;
 
 // Elements per 128-byte chunk for each precision.
 __host__ __device__ constexpr int chunk_elems(int prec) {
@@ -243,6 +253,24 @@ __device__ __forceinline__ void mfma_pair(f32x16& acc0, f32x16& acc1, const uint
     acc1 = c1;
 }
 
+// One FP8 key block against the query block over one chunk (two scaled
+// MFMAs, K = 64 each).
+template <bool FIRST>
+__device__ __forceinline__ void mfma_fp8_block(f32x16& acc, const uint4 (&a)[4], const uint4 (&b)[4], int sa, int sb) {
+    const f32x16 zero = {};
+    f32x16 c = FIRST ? zero : acc;
+#pragma unroll
+    for (int i = 0; i < 4; i += 2) {
+        const i32x8 vb = {(int)b[i].x, (int)b[i].y, (int)b[i].z, (int)b[i].w,
+                          (int)b[i + 1].x, (int)b[i + 1].y, (int)b[i + 1].z, (int)b[i + 1].w};
+        const i32x8 va = {(int)a[i].x, (int)a[i].y, (int)a[i].z, (int)a[i].w,
+                          (int)a[i + 1].x, (int)a[i + 1].y, (int)a[i + 1].z, (int)a[i + 1].w};
+        // operand format 0 = FP8 E4M3 for A and B
+        c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(va, vb, c, 0, 0, 0, sa, 0, sb);
+    }
+    acc = c;
+}
+
 // E8M0 encoding of a power-of-two float scale: its biased exponent.
 __device__ __forceinline__ int e8m0_of(float s) { return (int)((__float_as_uint(s) >> 23) & 0xffu); }
 
@@ -298,7 +326,11 @@ struct TileArgs {
 };
 
 template <int P>
-__global__ __launch_bounds__(TILE_THREADS) __attribute__((amdgpu_waves_per_eu(1, 1))) void knn_tile(TileArgs a) {
+__global__ __launch_bounds__(TileGeom<P>::THREADS) __attribute__((amdgpu_waves_per_eu(TileGeom<P>::WPE, TileGeom<P>::WPE))) void knn_tile(TileArgs a) {
+    constexpr int QB = TileGeom<P>::QB;
+    constexpr int TILE_WAVES = TileGeom<P>::WAVES;
+    constexpr int TT = TileGeom<P>::THREADS;
+    constexpr int RSTEP = TT / 8;  // rows between one thread's staged units
     // double-buffered tiles: one barrier per chunk, the next chunk's global
     // loads in flight while this chunk's MFMAs run
     __shared__ uint4 Ks[2][KT * ROW_UNITS];
@@ -307,7 +339,7 @@ __global__ __launch_bounds__(TILE_THREADS) __attribute__((amdgpu_waves_per_eu(1,
     // after the barrier that lets faster waves stage the following tiles
     __shared__ float Kn[3][KT];
     __shared__ float Ksc[3][KT];
-    __shared__ uint32_t hist_all[4][256];
+    __shared__ uint32_t hist_all[TILE_WAVES][256];
 
     const int t = threadIdx.x;
     const int l = t & 63;
@@ -322,7 +354,7 @@ __global__ __launch_bounds__(TILE_THREADS) __attribute__((amdgpu_waves_per_eu(1,
 
     // Rows of the query tile this thread loads (4 rows, unit t & 7).
     auto qrow_of = [&](int i) {
-        const int64_t m = (int64_t)qb * QB + (t >> 3) + 32 * i;
+        const int64_t m = (int64_t)qb * QB + (t >> 3) + RSTEP * i;
         const int64_t row = m < a.M ? load_qid(a.qids, a.m0, m) : 0;
         return row * row_units + (t & 7);
     };
@@ -358,9 +390,12 @@ __global__ __launch_bounds__(TILE_THREADS) __attribute__((amdgpu_waves_per_eu(1,
     // Global -> register staging of one chunk (8 key units + 4 query units per
     // thread) and register -> LDS parking.  Written as macros over plain
     // locals so the staging stays in registers.
+    // Global -> register staging of one chunk (4 key units + 4 query units
+    // per thread, rows 64 apart) and register -> LDS parking.  Written as
+    // macros over named locals so the staging stays in registers.
     uint4 pk0, pk1, pk2, pk3, pk4, pk5, pk6, pk7, pq0, pq1, pq2, pq3;
     const int64_t krow_ = (int64_t)(t >> 3) * row_units + (t & 7);
-    const int64_t kstep_ = 32 * row_units;
+    const int64_t kstep_ = RSTEP * row_units;
 #define ATSNE_LOAD_CHUNK(TILE, C)                                                                    \
     do {                                                                                             \
         const uint4* kb_ = a.Xp + (int64_t)(TILE) * KT * row_units + (int64_t)(C) * CHUNK_UNITS + krow_; \
@@ -368,10 +403,12 @@ __global__ __launch_bounds__(TILE_THREADS) __attribute__((amdgpu_waves_per_eu(1,
         pk1 = kb_[kstep_];                                                                           \
         pk2 = kb_[2 * kstep_];                                                                       \
         pk3 = kb_[3 * kstep_];                                                                       \
-        pk4 = kb_[4 * kstep_];                                                                       \
-        pk5 = kb_[5 * kstep_];                                                                       \
-        pk6 = kb_[6 * kstep_];                                                                       \
-        pk7 = kb_[7 * kstep_];                                                                       \
+        if (RSTEP == 32) {                                                                           \
+            pk4 = kb_[4 * kstep_];                                                                   \
+            pk5 = kb_[5 * kstep_];                                                                   \
+            pk6 = kb_[6 * kstep_];                                                                   \
+            pk7 = kb_[7 * kstep_];                                                                   \
+        }                                                                                            \
         const int64_t co_ = (int64_t)(C) * CHUNK_UNITS;                                              \
         pq0 = a.Xp[qoff0 + co_];                                                                     \
         pq1 = a.Xp[qoff1 + co_];                                                                     \
@@ -382,19 +419,21 @@ __global__ __launch_bounds__(TILE_THREADS) __attribute__((amdgpu_waves_per_eu(1,
     do {                                                                                             \
         uint4* ks_ = &Ks[BUF][(t >> 3) * ROW_UNITS + (t & 7)];                                      \
         ks_[0] = pk0;                                                                                \
-        ks_[32 * ROW_UNITS] = pk1;                                                                   \
-        ks_[64 * ROW_UNITS] = pk2;                                                                   \
-        ks_[96 * ROW_UNITS] = pk3;                                                                   \
-        ks_[128 * ROW_UNITS] = pk4;                                                                  \
-        ks_[160 * ROW_UNITS] = pk5;                                                                  \
-        ks_[192 * ROW_UNITS] = pk6;                                                                  \
-        ks_[224 * ROW_UNITS] = pk7;                                                                  \
+        ks_[RSTEP * ROW_UNITS] = pk1;                                                                \
+        ks_[2 * RSTEP * ROW_UNITS] = pk2;                                                            \
+        ks_[3 * RSTEP * ROW_UNITS] = pk3;                                                            \
+        if (RSTEP == 32) {                                                                           \
+            ks_[4 * RSTEP * ROW_UNITS] = pk4;                                                        \
+            ks_[5 * RSTEP * ROW_UNITS] = pk5;                                                        \
+            ks_[6 * RSTEP * ROW_UNITS] = pk6;                                                        \
+            ks_[7 * RSTEP * ROW_UNITS] = pk7;                                                        \
+        }                                                                                            \
         uint4* qs_ = &Qs[BUF][(t >> 3) * ROW_UNITS + (t & 7)];                                      \
         qs_[0] = pq0;                                                                                \
-        qs_[32 * ROW_UNITS] = pq1;                                                                   \
-        qs_[64 * ROW_UNITS] = pq2;                                                                   \
-        qs_[96 * ROW_UNITS] = pq3;                                                                   \
-        if ((C) == 0) {                                                                              \
+        qs_[RSTEP * ROW_UNITS] = pq1;                                                                \
+        qs_[2 * RSTEP * ROW_UNITS] = pq2;                                                            \
+        qs_[3 * RSTEP * ROW_UNITS] = pq3;                                                            \
+        if ((C) == 0 && t < KT) {                                                                    \
             Kn[(TILE) % 3][t] = a.norms[(int64_t)(TILE) * KT + t];                                  \
             if (P == ATSNE_PREC_FP8_E4M3) Ksc[(TILE) % 3][t] = a.scales[(int64_t)(TILE) * KT + t];  \
         }                                                                                            \
@@ -407,30 +446,28 @@ __global__ __launch_bounds__(TILE_THREADS) __attribute__((amdgpu_waves_per_eu(1,
     auto compute = [&](int buf, auto first_tag) __attribute__((always_inline)) {
         constexpr bool FIRST = decltype(first_tag)::value;
         const uint4* K = Ks[buf];
-        uint4 bq[4], ca0[4], ca1[4], na0[4], na1[4];
+        uint4 bq[4], ca0[4], ca1[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) bq[i] = Qs[buf][qloc * ROW_UNITS + chunk_unit<P>(l, i)];
+        if constexpr (P == ATSNE_PREC_FP8_E4M3) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            ca0[i] = K[(0 + (l & 31)) * ROW_UNITS + chunk_unit<P>(l, i)];
-            ca1[i] = K[(32 + (l & 31)) * ROW_UNITS + chunk_unit<P>(l, i)];
-        }
+            for (int b = 0; b < NKB; ++b) {
 #pragma unroll
-        for (int pr = 0; pr < NKB / 2; ++pr) {
-            if (pr + 1 < NKB / 2) {
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    na0[i] = K[(64 * (pr + 1) + (l & 31)) * ROW_UNITS + chunk_unit<P>(l, i)];
-                    na1[i] = K[(64 * (pr + 1) + 32 + (l & 31)) * ROW_UNITS + chunk_unit<P>(l, i)];
-                }
+                for (int i = 0; i < 4; ++i) ca0[i] = K[(32 * b + (l & 31)) * ROW_UNITS + chunk_unit<P>(l, i)];
+                mfma_fp8_block<FIRST>(acc[b], ca0, bq, ksc_e8[b], sq_e8);
+                // keep the next block's operand reads from being hoisted over
+                // these MFMAs (register budget at two waves per SIMD)
+                __builtin_amdgcn_sched_barrier(0);
             }
-            mfma_pair<P, FIRST>(acc[2 * pr], acc[2 * pr + 1], ca0, ca1, bq, ksc_e8[2 * pr], ksc_e8[2 * pr + 1], sq_e8);
-            if (pr + 1 < NKB / 2) {
+        } else {
+#pragma unroll
+            for (int pr = 0; pr < NKB / 2; ++pr) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    ca0[i] = na0[i];
-                    ca1[i] = na1[i];
+                    ca0[i] = K[(64 * pr + (l & 31)) * ROW_UNITS + chunk_unit<P>(l, i)];
+                    ca1[i] = K[(64 * pr + 32 + (l & 31)) * ROW_UNITS + chunk_unit<P>(l, i)];
                 }
+                mfma_pair<P, FIRST>(acc[2 * pr], acc[2 * pr + 1], ca0, ca1, bq, 127, 127, 127);
             }
         }
     };
@@ -693,14 +730,20 @@ __device__ uint64_t union_threshold(Each each, int take, int total, uint32_t* hi
 }
 
 // knn_select: one wave (workgroup of 64) per query row.
+// LDS of knn_select for up to kcap candidates (sized at launch).
+__host__ __device__ constexpr size_t select_lds_bytes(int kcap) {
+    return 256 * 4 + (size_t)kcap * (8 + 8 + 4 + 4) + 16;
+}
+
 template <int P>
-__global__ __launch_bounds__(64) void knn_select(SelArgs a) {
-    __shared__ uint32_t hist[256];
-    __shared__ int32_t cj[MAX_KC];
-    __shared__ float cd[MAX_KC];
-    __shared__ uint64_t sorted[MAX_KC];
-    __shared__ double dd[MAX_KC];
-    __shared__ int32_t ncand;
+__global__ __launch_bounds__(64) void knn_select(SelArgs a, int kcap) {
+    extern __shared__ __align__(16) unsigned char sel_lds[];
+    double* dd = reinterpret_cast<double*>(sel_lds);
+    uint64_t* sorted = reinterpret_cast<uint64_t*>(dd + kcap);
+    uint32_t* hist = reinterpret_cast<uint32_t*>(sorted + kcap);
+    int32_t* cj = reinterpret_cast<int32_t*>(hist + 256);
+    float* cd = reinterpret_cast<float*>(cj + kcap);
+    int32_t& ncand = *reinterpret_cast<int32_t*>(cd + kcap);
     const int l = lane_id();
     const int64_t m = blockIdx.x;
     if (m >= a.M) return;
@@ -1063,8 +1106,9 @@ atsne_status corpus_prep(const Corpus& c, int64_t r0, int64_t r1, int64_t n_live
     return ATSNE_OK;
 }
 
-SearchPlan plan_search(int64_t M, int64_t key_lo, int64_t key_hi, int k_max, int kc_max, int s_max) {
+SearchPlan plan_search(int prec, int64_t M, int64_t key_lo, int64_t key_hi, int k_max, int kc_max, int s_max) {
     SearchPlan p;
+    p.qb = qb_of(prec);
     p.M = M;
     p.k_max = k_max;
     p.kc_max = kc_max;
@@ -1072,14 +1116,14 @@ SearchPlan plan_search(int64_t M, int64_t key_lo, int64_t key_hi, int k_max, int
     p.tile_hi = (int)ceil_div(key_hi, KT);
     const int total_tiles = std::max(1, p.tile_hi - p.tile_lo);
     p.cap = (int)align_up((size_t)(kc_max + KT + std::max(kc_max, 128)), 64);
-    p.MB = (int)ceil_div(std::max<int64_t>(M, 1), QB);
+    p.MB = (int)ceil_div(std::max<int64_t>(M, 1), p.qb);
     int S = pick_splits(p.MB, total_tiles, device_cu_count());
     if (s_max > 0) S = std::min(S, s_max);
     p.tiles_per_split = (int)ceil_div(total_tiles, S);
     p.S = (int)ceil_div(total_tiles, p.tiles_per_split);
     Arena a;
-    a.take<uint64_t>((size_t)p.MB * QB * p.S * p.cap);
-    a.take<int32_t>((size_t)p.MB * QB * p.S);
+    a.take<uint64_t>((size_t)p.MB * p.qb * p.S * p.cap);
+    a.take<int32_t>((size_t)p.MB * p.qb * p.S);
     a.take<int32_t>(64);
     a.take<int32_t>(std::max<int64_t>(M, 1));
     p.ws_bytes = a.used;
@@ -1096,8 +1140,8 @@ struct SearchWs {
 static SearchWs carve(const SearchPlan& p, void* ws) {
     Arena a(ws, p.ws_bytes);
     SearchWs w;
-    w.slots = a.take<uint64_t>((size_t)p.MB * QB * p.S * p.cap);
-    w.counts = a.take<int32_t>((size_t)p.MB * QB * p.S);
+    w.slots = a.take<uint64_t>((size_t)p.MB * p.qb * p.S * p.cap);
+    w.counts = a.take<int32_t>((size_t)p.MB * p.qb * p.S);
     w.misc = a.take<int32_t>(64);
     w.scan_list = a.take<int32_t>(std::max<int64_t>(p.M, 1));
     return w;
@@ -1124,7 +1168,7 @@ static atsne_status launch_tile(const Corpus& c, const Batch& b, const SearchPla
     t.kc = b.kc;
     t.tau0 = b.tau0;
     t.tau0_stride = b.tau0_stride;
-    t.MB = (int)ceil_div(b.M, QB);
+    t.MB = (int)ceil_div(b.M, TileGeom<P>::QB);
     t.S = p.S;
     t.tiles_per_split = p.tiles_per_split;
     t.tile_lo = p.tile_lo;
@@ -1133,7 +1177,7 @@ static atsne_status launch_tile(const Corpus& c, const Batch& b, const SearchPla
     t.slots = w.slots;
     t.counts = w.counts;
     ProfScope ps_(b.tau0 ? "knn_tile_reverse" : "knn_tile", st);
-    knn_tile<P><<<dim3((unsigned)(t.MB * p.S)), dim3(TILE_THREADS), 0, st>>>(t);
+    knn_tile<P><<<dim3((unsigned)(t.MB * p.S)), dim3(TileGeom<P>::THREADS), 0, st>>>(t);
     ATSNE_LAUNCH_CHECK();
     return ATSNE_OK;
 }
@@ -1190,15 +1234,17 @@ atsne_status knn_search(const Corpus& c, const Batch& b, const SearchPlan& p, vo
     const SelArgs s = sel_args(c, b, p, w);
     {
         ProfScope ps_("knn_select", st);
+        const int kcap = p.kc_max;
+        const size_t lds = select_lds_bytes(kcap);
         switch (c.prec) {
             case ATSNE_PREC_FP32:
-                knn_select<ATSNE_PREC_FP32><<<dim3((unsigned)b.M), dim3(64), 0, st>>>(s);
+                knn_select<ATSNE_PREC_FP32><<<dim3((unsigned)b.M), dim3(64), lds, st>>>(s, kcap);
                 break;
             case ATSNE_PREC_BF16:
-                knn_select<ATSNE_PREC_BF16><<<dim3((unsigned)b.M), dim3(64), 0, st>>>(s);
+                knn_select<ATSNE_PREC_BF16><<<dim3((unsigned)b.M), dim3(64), lds, st>>>(s, kcap);
                 break;
             default:
-                knn_select<ATSNE_PREC_FP8_E4M3><<<dim3((unsigned)b.M), dim3(64), 0, st>>>(s);
+                knn_select<ATSNE_PREC_FP8_E4M3><<<dim3((unsigned)b.M), dim3(64), lds, st>>>(s, kcap);
         }
         ATSNE_LAUNCH_CHECK();
     }
@@ -1261,13 +1307,21 @@ static atsne_status make_plan(int64_t N, int64_t M, int32_t D, int prec, int k, 
     p.M = M;
     p.D = D;
     p.b_corpus = corpus_bytes(prec, N, D);
-    // Batch the queries so the candidate slots stay within ~2 GiB.
-    SearchPlan full = plan_search(std::max<int64_t>(M, 1), 0, N, k, kc);
+    // Keep the candidate slots within ~2 GiB: fewer key splits first, then
+    // batches of query rows.
+    const size_t slot_budget = (size_t)2 << 30;
+    const int64_t Mq = std::max<int64_t>(M, 1);
+    SearchPlan full = plan_search(prec, Mq, 0, N, k, kc);
+    if (full.ws_bytes > slot_budget && full.S > 1) {
+        const int64_t s_fit = (int64_t)(slot_budget / ((size_t)Mq * full.cap * 8));
+        full = plan_search(prec, Mq, 0, N, k, kc, (int)std::max<int64_t>(1, std::min<int64_t>(full.S, s_fit)));
+    }
+    const int qb = qb_of(prec);
     const size_t per_row = (size_t)full.S * full.cap * 8;
-    int64_t max_rows = (int64_t)(((size_t)2 << 30) / per_row);
-    max_rows = std::max<int64_t>(QB, max_rows / QB * QB);
-    p.Mb = std::min<int64_t>(std::max<int64_t>(M, 1), max_rows);
-    p.sp = p.Mb < std::max<int64_t>(M, 1) ? plan_search(p.Mb, 0, N, k, kc) : full;
+    int64_t max_rows = (int64_t)(slot_budget / per_row);
+    max_rows = std::max<int64_t>(qb, max_rows / qb * qb);
+    p.Mb = std::min<int64_t>(Mq, max_rows);
+    p.sp = p.Mb < Mq ? plan_search(prec, p.Mb, 0, N, k, kc, full.S) : full;
     p.total = align_up(p.b_corpus, 256) + p.sp.ws_bytes;
     return ATSNE_OK;
 }

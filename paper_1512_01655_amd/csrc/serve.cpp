@@ -244,8 +244,8 @@ atsne_status launch_batch(atsne_server* s, BatchSlot& b, std::vector<Seg>& segs,
     }
     ATSNE_HIP(hipMemcpyAsync(b.d_desc, b.h_desc, sizeof(int32_t) * 4 * R, hipMemcpyHostToDevice, b.st));
     const int s_fit = 64;
-    SearchPlan p = plan_search(rows, 0, key_hi, s->kmax, s->kcmax, s_fit);
-    while (p.ws_bytes > b.ws_bytes && p.S > 1) p = plan_search(rows, 0, key_hi, s->kmax, s->kcmax, p.S - 1);
+    SearchPlan p = plan_search(ATSNE_PREC_FP32, rows, 0, key_hi, s->kmax, s->kcmax, s_fit);
+    while (p.ws_bytes > b.ws_bytes && p.S > 1) p = plan_search(ATSNE_PREC_FP32, rows, 0, key_hi, s->kmax, s->kcmax, p.S - 1);
     ATSNE_REQUIRE(p.ws_bytes <= b.ws_bytes, ATSNE_E_NOMEM, "batch workspace too small");
     Batch bt;
     bt.M = rows;
@@ -308,8 +308,8 @@ atsne_status commit_insert(atsne_server* s, Request& r) {
     // 2. Eq. 13 over the residents that existed before this insert
     ATSNE_HIP(hipMemsetAsync(r.n_changed_dev, 0, sizeof(int32_t), st));
     if (r0 > 0) {
-        SearchPlan p = plan_search(r0, r0, r0 + B, K, K);
-        while (p.ws_bytes > s->rev_ws_bytes && p.S > 1) p = plan_search(r0, r0, r0 + B, K, K, p.S - 1);
+        SearchPlan p = plan_search(ATSNE_PREC_FP32, r0, r0, r0 + B, K, K);
+        while (p.ws_bytes > s->rev_ws_bytes && p.S > 1) p = plan_search(ATSNE_PREC_FP32, r0, r0, r0 + B, K, K, p.S - 1);
         ATSNE_REQUIRE(p.ws_bytes <= s->rev_ws_bytes, ATSNE_E_NOMEM, "reverse workspace too small");
         Batch bt;
         bt.M = r0;
@@ -541,7 +541,7 @@ extern "C" atsne_status atsne_serve_create(const atsne_serve_config* cfg, const 
     const int64_t R = s->max_batch_rows;
     {
         // batch workspace: enough for the largest batch with a few splits
-        SearchPlan p = plan_search(R, 0, cap, s->kmax, s->kcmax, 4);
+        SearchPlan p = plan_search(ATSNE_PREC_FP32, R, 0, cap, s->kmax, s->kcmax, 4);
         for (auto& b : s->slot) {
             b.ws_bytes = p.ws_bytes;
             if ((st = alloc_dev(&b.ws, b.ws_bytes)) != ATSNE_OK) return fail(st);
@@ -556,7 +556,7 @@ extern "C" atsne_status atsne_serve_create(const atsne_serve_config* cfg, const 
                 return fail(ATSNE_E_HIP);
             }
         }
-        SearchPlan rp = plan_search(cap, 0, 4096 + KNN_KT, K0, K0, 1);
+        SearchPlan rp = plan_search(ATSNE_PREC_FP32, cap, 0, 4096 + KNN_KT, K0, K0, 1);
         s->rev_ws_bytes = rp.ws_bytes;
         if ((st = alloc_dev(&s->rev_ws, s->rev_ws_bytes)) != ATSNE_OK) return fail(st);
     }
@@ -572,7 +572,7 @@ extern "C" atsne_status atsne_serve_create(const atsne_serve_config* cfg, const 
     }
     if ((st = corpus_prep(s->corpus, 0, cap, N, cs)) != ATSNE_OK) return fail(st);
     {
-        SearchPlan p = plan_search(std::min<int64_t>(N, 65536), 0, N, K0, s->kc0);
+        SearchPlan p = plan_search(ATSNE_PREC_FP32, std::min<int64_t>(N, 65536), 0, N, K0, s->kc0);
         void* ws = nullptr;
         if ((st = alloc_dev(&ws, p.ws_bytes)) != ATSNE_OK) return fail(st);
         for (int64_t m0 = 0; m0 < N && st == ATSNE_OK; m0 += p.M) {
