@@ -30,7 +30,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="imagelike", choices=["imagelike", "mixture"])
+    ap.add_argument("--workload", default="imagelike", choices=["imagelike", "mixture", "aniso"])
     ap.add_argument("--no-bf16", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
@@ -45,6 +45,40 @@ def parse():
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+KERNEL_SOURCES = ["paper_1512_01655_amd/csrc/knn.hip", "paper_1512_01655_amd/csrc/wave.h",
+                  "paper_1512_01655_amd/csrc/knn_internal.h", "paper_1512_01655_amd/csrc/common.h"]
+TRAFFIC_FILE = "profiles/knn_tile_traffic.txt"
+
+
+def kernel_source_hash():
+    import hashlib
+
+    root = os.path.dirname(os.path.abspath(__file__))
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(root, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, prec):
+    """HBM bytes per knn_tile launch from the committed counter summary, or
+    None when it was taken on other kernel sources or another workload."""
+    root = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(root, TRAFFIC_FILE)
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            rec[k.strip()] = v.strip()
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    key = "%s_%s_bytes_per_launch" % (workload, prec)
+    return int(float(rec[key])) if key in rec else None
 
 
 def run_path(A, torch, Xt, mu, k, prec, steps, warmup):
@@ -185,10 +219,13 @@ def main():
     if a.workload == "imagelike":
         X = datagen.image_like()
         name = "imagelike_N70000_D784_mu30_k90"
-    else:
+    elif a.workload == "mixture":
         X = datagen.mixture_isotropic()
         name = "mixture10_N2000_D50_mu30_k90"
-    mu, k = 30.0, 90
+    else:
+        X = datagen.mixture_anisotropic()
+        name = "aniso50_N1000000_D128_mu50_k150"
+    mu, k = (50.0, 150) if a.workload == "aniso" else (30.0, 90)
     N, D = X.shape
     Xt = torch.from_numpy(X).cuda()
     log("bench: %s on %s" % (name, torch.cuda.get_device_name(0)))
@@ -199,8 +236,8 @@ def main():
         src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
         dst = src.clone()
         torch.cuda.synchronize()
-        log("profile: knn %s N=%d D=%d k=%d; copy kernel moved %d bytes read + %d bytes written" % (
-            a.profile_kernel, N, D, k, src.numel() * 4, dst.numel() * 4))
+        log("profile: knn %s N=%d D=%d k=%d; copy kernel moved %d bytes read + %d bytes written; "
+            "kernel sources %s" % (a.profile_kernel, N, D, k, src.numel() * 4, dst.numel() * 4, kernel_source_hash()))
         return
 
     r = run_path(A, torch, Xt, mu, k, "fp32", a.steps, a.warmup)
@@ -224,7 +261,7 @@ def main():
                    "k_cand": k + max(32, k // 2)},
         "roofline": {"bound": "mfma", "kernel": "knn_tile", "achieved": round(achieved, 2),
                      "peak": PEAK["fp32"], "unit": "TFLOP/s", "frac": round(achieved / PEAK["fp32"], 4),
-                     "traffic": None, "avg_launch_ms": round(tile_avg_s * 1e3, 3),
+                     "traffic": measured_traffic(a.workload, "fp32"), "avg_launch_ms": round(tile_avg_s * 1e3, 3),
                      "launches_per_step": tile_n / a.steps,
                      "algorithmic": "2*N*D FLOP per query point x N queries per step, N=%d, D=%d" % (N, D)},
         "stages_ms": stages_ms,
@@ -241,7 +278,8 @@ def main():
             "speedup_vs_fp32": round(vb / value, 3), "k_cand": 2 * k,
             "stages_ms": {kname: round(v[0] / a.steps, 3) for kname, v in rb["stages"].items()},
             "roofline": {"bound": "mfma", "kernel": "knn_tile", "achieved": round(ach_b, 2), "peak": PEAK["bf16"],
-                         "unit": "TFLOP/s", "frac": round(ach_b / PEAK["bf16"], 4)},
+                         "unit": "TFLOP/s", "frac": round(ach_b / PEAK["bf16"], 4),
+                         "traffic": measured_traffic(a.workload, "bf16")},
             "agree_with_fp32_rows": float((rb["idx"] == r["idx"]).all(1).float().mean().item()),
         }
         log("bf16: %.1f points/s (x%.2f)" % (vb, vb / value))

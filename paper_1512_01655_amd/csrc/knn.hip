@@ -495,6 +495,17 @@ __global__ __launch_bounds__(TileGeom<P>::THREADS) __attribute__((amdgpu_waves_p
         const float* kn = Kn[tile % 3];
 #pragma unroll
         for (int b = 0; b < NKB; ++b) {
+            // block-level test first: one compare and one branch for the 16
+            // candidates a lane holds in this key block (almost always none
+            // passes once the threshold has settled)
+            float dmin = INFINITY;
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const float4 nj = *reinterpret_cast<const float4*>(&kn[32 * b + 8 * g + 4 * (l >> 5)]);
+                dmin = fminf(dmin, fminf(fminf(fmaf(-2.0f, acc[b][4 * g + 0], nj.x), fmaf(-2.0f, acc[b][4 * g + 1], nj.y)),
+                                         fminf(fmaf(-2.0f, acc[b][4 * g + 2], nj.z), fmaf(-2.0f, acc[b][4 * g + 3], nj.w))));
+            }
+            if (!ballot(dmin < tau)) continue;
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
                 const int kl = 32 * b + 8 * g + 4 * (l >> 5);
