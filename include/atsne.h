@@ -133,7 +133,10 @@ atsne_status atsne_knn_subset(const float* X, int64_t N, int32_t D, int64_t ld, 
  *   flags      [N] uint8 in/out (may be NULL): NOT_CONVERGED and DEGENERATE
  *              are OR-ed into the existing bits.
  * Rows whose minimum-distance multiplicity m satisfies m >= mu cannot reach
- * mu: they get the beta -> inf limit (uniform over the m) and DEGENERATE. */
+ * mu: they get the beta -> inf limit (uniform over the m) and DEGENERATE.
+ * An entry of +inf is absent (a removed neighbour, Sec. 5.3): it gets p = 0
+ * and the row is calibrated over its present entries; a row with no more
+ * than mu present entries is uniform over them and DEGENERATE. */
 atsne_status atsne_calibrate_p(const float* nbr_d2, int64_t N, int32_t k, float perplexity, float tol,
                                int32_t max_iter, int32_t strict, float* P_cond, float* beta, float* perp,
                                uint8_t* flags, void* stream);
@@ -177,9 +180,15 @@ atsne_status atsne_symmetrize_csr(const int64_t* in_ptr, const int32_t* in_col, 
  *   refine  (Sec. 4.3, Sec. 5.1): the exact neighbourhood and P row of a
  *           user selection of M resident points is recomputed at a requested
  *           perplexity (K_i = floor(3 mu_i) per row).
- * Requests carry an epoch: a request sees exactly the corpus committed
- * before it (inserts commit in arrival order), so its result does not depend
- * on what else shares the GPU. */
+ *   delete  (Sec. 5.3): points leave the corpus; every resident list drops
+ *           them without a replacement (the hole can be filled by later
+ *           inserts), the row's precision rho_i falls by 1/K per removed
+ *           neighbour, and changed rows are re-calibrated.  Inserting new
+ *           points and deleting the oldest gives the sliding window of Sec. 8.
+ * Inserts and deletes are commits, applied in arrival order.  Every request
+ * carries a view (`epoch`): the number of commits submitted before it.  A
+ * request sees exactly the corpus those commits define, so its result does
+ * not depend on what else shares the GPU. */
 
 typedef struct atsne_server atsne_server;
 
@@ -193,7 +202,7 @@ typedef struct atsne_serve_config {
 
 typedef struct atsne_result {
     uint64_t req_id;
-    int32_t kind;            /* 0 insert, 1 refine */
+    int32_t kind;            /* 0 insert, 1 refine, 2 delete */
     int32_t status;          /* atsne_status of the request */
     uint64_t epoch;          /* corpus version the request ran against */
     int64_t n_rows;          /* rows in the result (B or M) */
@@ -205,8 +214,8 @@ typedef struct atsne_result {
     const float* P_cond;     /* device [n_rows x k] */
     const float* beta;       /* device [n_rows] */
     const uint8_t* flags;    /* device [n_rows] */
-    int64_t n_changed;       /* insert: resident rows whose list changed (Eq. 13) */
-    const int32_t* changed;  /* device [n_changed] corpus ids (insert only) */
+    int64_t n_changed;       /* insert/delete: resident rows whose list changed */
+    const int32_t* changed;  /* device [n_changed] corpus ids (insert/delete) */
     double t_submit_ms, t_admit_ms, t_complete_ms; /* host clock, ms since server start */
 } atsne_result;
 
@@ -229,6 +238,8 @@ atsne_status atsne_serve_create(const atsne_serve_config* cfg, const float* corp
 /* Queue an insert of B points X_new [B x D] (device FP32).  Returns at once
  * with *req_id; the data is copied before return. */
 atsne_status atsne_serve_submit_insert(atsne_server* s, const float* X_new, int32_t B, uint64_t* req_id);
+/* Queue a delete of M corpus ids (host int32 array, alive at submission). */
+atsne_status atsne_serve_submit_delete(atsne_server* s, const int32_t* ids_host, int32_t M, uint64_t* req_id);
 /* Queue a refine of M corpus ids (host int32 array) at perplexity mu. */
 atsne_status atsne_serve_submit_refine(atsne_server* s, const int32_t* ids_host, int32_t M, float perplexity,
                                        uint64_t* req_id);
@@ -239,12 +250,16 @@ atsne_status atsne_serve_wait(atsne_server* s, uint64_t req_id, atsne_result* ou
 /* Free a completed request's result buffers (server-owned until then). */
 atsne_status atsne_serve_release(atsne_server* s, uint64_t req_id);
 atsne_status atsne_serve_stats_get(atsne_server* s, atsne_serve_stats* out);
-/* Snapshot of the server's state at the latest committed epoch: copies the
- * corpus rows and fixed-k lists (rows refined at another k are reported with
- * their own k via k_rows) into caller device buffers of capacity cap_rows.
+/* Snapshot of the server's state once every submitted commit is applied:
+ * copies the corpus rows, the resident k-lists (absent entries are index -1,
+ * distance +inf, P 0; deleted rows are all absent), their conditional P and
+ * beta, the per-row precision rho (present entries / k: 1 for an exact row,
+ * 1/k less per removed neighbour, 0 for a deleted row) and the alive flags
+ * into caller device buffers of capacity cap_rows (any pointer may be NULL).
  * Synchronises. */
 atsne_status atsne_serve_snapshot(atsne_server* s, int64_t cap_rows, float* corpus, int32_t* nbr_idx,
-                                  float* nbr_d2, int64_t* n_rows, uint64_t* epoch);
+                                  float* nbr_d2, float* P_cond, float* beta, float* rho, uint8_t* alive,
+                                  int64_t* n_rows, uint64_t* epoch);
 /* Destroy: waits for in-flight work; ATSNE_E_BUSY if results are unreleased
  * and force == 0. */
 atsne_status atsne_serve_destroy(atsne_server* s, int32_t force);

@@ -26,7 +26,8 @@ EXPORTS = [
     "atsne_knn_workspace_size", "atsne_knn", "atsne_knn_subset",
     "atsne_calibrate_p",
     "atsne_symmetrize_workspace_size", "atsne_symmetrize", "atsne_symmetrize_csr",
-    "atsne_serve_create", "atsne_serve_submit_insert", "atsne_serve_submit_refine", "atsne_serve_poll",
+    "atsne_serve_create", "atsne_serve_submit_insert", "atsne_serve_submit_refine", "atsne_serve_submit_delete",
+    "atsne_serve_poll",
     "atsne_serve_wait", "atsne_serve_release", "atsne_serve_stats_get", "atsne_serve_snapshot",
     "atsne_serve_destroy",
 ]
@@ -91,11 +92,12 @@ def load(path: Path | None = None) -> ctypes.CDLL:
         "atsne_serve_create": [_p, _p, _i64, _i32, _f32, _p],
         "atsne_serve_submit_insert": [_p, _p, _i32, _p],
         "atsne_serve_submit_refine": [_p, _p, _i32, _f32, _p],
+        "atsne_serve_submit_delete": [_p, _p, _i32, _p],
         "atsne_serve_poll": [_p, ctypes.c_uint64, _p],
         "atsne_serve_wait": [_p, ctypes.c_uint64, _p],
         "atsne_serve_release": [_p, ctypes.c_uint64],
         "atsne_serve_stats_get": [_p, _p],
-        "atsne_serve_snapshot": [_p, _i64, _p, _p, _p, _p, _p],
+        "atsne_serve_snapshot": [_p, _i64, _p, _p, _p, _p, _p, _p, _p, _p, _p],
         "atsne_serve_destroy": [_p, _i32],
     }
     for name, args in sig.items():
@@ -302,22 +304,32 @@ class Server:
                                                 ctypes.byref(rid)))
         return rid.value
 
+    def delete(self, ids) -> int:
+        """Remove live points (Sec. 5.3); later requests no longer see them."""
+        import numpy as np
+
+        ids = np.ascontiguousarray(ids, dtype=np.int32)
+        rid = ctypes.c_uint64()
+        _check(load().atsne_serve_submit_delete(self.h, ids.ctypes.data_as(_p), ids.size, ctypes.byref(rid)))
+        return rid.value
+
     @staticmethod
     def _result(r: Result, fetch: bool):
         import numpy as np
 
-        out = dict(req_id=r.req_id, kind="insert" if r.kind == 0 else "refine", status=r.status, epoch=r.epoch,
+        out = dict(req_id=r.req_id, kind=("insert", "refine", "delete")[r.kind], status=r.status, epoch=r.epoch,
                    n_rows=r.n_rows, k=r.k, perplexity=r.perplexity, n_changed=r.n_changed,
                    t_submit_ms=r.t_submit_ms, t_admit_ms=r.t_admit_ms, t_complete_ms=r.t_complete_ms)
         if fetch and r.status == OK:
             n, k = r.n_rows, r.k
             out["row_ids"] = _d2h(r.row_ids, (n,), np.int32)
-            out["idx"] = _d2h(r.nbr_idx, (n, k), np.int32)
-            out["d2"] = _d2h(r.nbr_d2, (n, k), np.float32)
-            out["P"] = _d2h(r.P_cond, (n, k), np.float32)
-            out["beta"] = _d2h(r.beta, (n,), np.float32)
-            out["flags"] = _d2h(r.flags, (n,), np.uint8)
-            if r.kind == 0:
+            if r.kind != 2:
+                out["idx"] = _d2h(r.nbr_idx, (n, k), np.int32)
+                out["d2"] = _d2h(r.nbr_d2, (n, k), np.float32)
+                out["P"] = _d2h(r.P_cond, (n, k), np.float32)
+                out["beta"] = _d2h(r.beta, (n,), np.float32)
+                out["flags"] = _d2h(r.flags, (n,), np.uint8)
+            if r.kind != 1:
                 out["changed"] = _d2h(r.changed, (r.n_changed,), np.int32)
         return out
 
@@ -343,20 +355,24 @@ class Server:
         return {name: getattr(st, name) for name, _ in ServeStats._fields_}
 
     def snapshot(self):
-        """(corpus, idx, d2) numpy copies of the committed state."""
-        import numpy as np
-
+        """(corpus, idx, d2, P, beta, rho, alive) numpy copies of the state once
+        every submitted insert and delete is applied."""
         st = self.stats()
         cap = st["corpus_rows"]
         K = int(math.floor(3 * self.perplexity))
         X = torch.empty((cap, self.D), dtype=torch.float32, device="cuda")
         idx = torch.empty((cap, K), dtype=torch.int32, device="cuda")
         d2 = torch.empty((cap, K), dtype=torch.float32, device="cuda")
+        P = torch.empty((cap, K), dtype=torch.float32, device="cuda")
+        beta = torch.empty((cap,), dtype=torch.float32, device="cuda")
+        rho = torch.empty((cap,), dtype=torch.float32, device="cuda")
+        alive = torch.empty((cap,), dtype=torch.uint8, device="cuda")
         n, ep = ctypes.c_int64(), ctypes.c_uint64()
-        _check(load().atsne_serve_snapshot(self.h, cap, _ptr(X), _ptr(idx), _ptr(d2), ctypes.byref(n),
-                                           ctypes.byref(ep)))
+        torch.cuda.synchronize()
+        _check(load().atsne_serve_snapshot(self.h, cap, _ptr(X), _ptr(idx), _ptr(d2), _ptr(P), _ptr(beta), _ptr(rho),
+                                           _ptr(alive), ctypes.byref(n), ctypes.byref(ep)))
         n = n.value
-        return X[:n].cpu().numpy(), idx[:n].cpu().numpy(), d2[:n].cpu().numpy()
+        return tuple(t[:n].cpu().numpy() for t in (X, idx, d2, P, beta, rho, alive))
 
     def close(self, force: bool = True):
         if getattr(self, "h", None):

@@ -42,38 +42,47 @@ __global__ __launch_bounds__(256) void calibrate_rows(const float* __restrict__ 
         int c = l + WAVE * r;
         dl[r] = c < k ? d[c] : INFINITY;
     }
+    // +inf marks an absent entry (a deleted neighbour): weight 0
     float mn = INFINITY;
 #pragma unroll
     for (int r = 0; r < R; ++r) mn = fminf(mn, dl[r]);
     mn = wave_min(mn);
-    float sum = 0.f, zeros = 0.f;
+    float sum = 0.f, zeros = 0.f, live = 0.f;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        int c = l + WAVE * r;
-        if (c < k) {
+        if (dl[r] < INFINITY) {
             dl[r] -= mn;  // delta_j >= 0, min 0: Z >= 1, no overflow
             sum += dl[r];
             zeros += dl[r] == 0.f ? 1.f : 0.f;
+            live += 1.f;
         }
     }
     sum = wave_sum(sum);
     zeros = wave_sum(zeros);
+    live = wave_sum(live);
 
     uint8_t fl = 0;
     float b = 0.f;
     float w[R];
     float Z = 0.f;
-    if (sum == 0.f) {
-        // all neighbours equidistant: every beta gives H = ln k
+    if (live == 0.f) {
+        // no neighbour left
 #pragma unroll
-        for (int r = 0; r < R; ++r) w[r] = (l + WAVE * r) < k ? 1.f : 0.f;
-        Z = (float)k;
+        for (int r = 0; r < R; ++r) w[r] = 0.f;
+        Z = 1.f;
+        fl |= ATSNE_FLAG_DEGENERATE;
+    } else if (sum == 0.f || !(mu < live)) {
+        // all neighbours equidistant (H = ln live for every beta), or too few
+        // left to reach mu: uniform over the present entries
+#pragma unroll
+        for (int r = 0; r < R; ++r) w[r] = dl[r] < INFINITY ? 1.f : 0.f;
+        Z = live;
         b = 0.f;
         fl |= ATSNE_FLAG_DEGENERATE;
     } else if (zeros >= mu) {
         // H falls to ln m >= ln mu only as beta -> inf: take the limit
 #pragma unroll
-        for (int r = 0; r < R; ++r) w[r] = ((l + WAVE * r) < k && dl[r] == 0.f) ? 1.f : 0.f;
+        for (int r = 0; r < R; ++r) w[r] = dl[r] == 0.f ? 1.f : 0.f;
         Z = zeros;
         b = INFINITY;
         fl |= ATSNE_FLAG_DEGENERATE;
@@ -84,17 +93,17 @@ __global__ __launch_bounds__(256) void calibrate_rows(const float* __restrict__ 
             float z = 0.f, s = 0.f;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                float e = expf(-bb * dl[r]);  // delta = inf (padding) gives 0
+                float e = expf(-bb * dl[r]);  // delta = inf (absent or padding) gives 0
                 w[r] = e;
                 z += e;
-                s = fmaf(e, (l + WAVE * r) < k ? dl[r] : 0.f, s);
+                s = fmaf(e, dl[r] < INFINITY ? dl[r] : 0.f, s);
             }
             z = wave_sum(z);
             s = wave_sum(s);
             Zo = z;
             return logf(z) + bb * (s / z);
         };
-        float lo = 0.f, hi = (float)k / sum;  // 1 / mean(delta)
+        float lo = 0.f, hi = live / sum;  // 1 / mean(delta)
         int it = 0;
         float h = entropy(hi, Z);
         while (h > target && it < max_iter) {

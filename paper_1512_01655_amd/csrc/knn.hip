@@ -275,10 +275,31 @@ __device__ __forceinline__ void mfma_fp8_block(f32x16& acc, const uint4 (&a)[4],
 __device__ __forceinline__ int e8m0_of(float s) { return (int)((__float_as_uint(s) >> 23) & 0xffu); }
 
 // Shrink one candidate slot to its best `kc` keys (wave-wide). Returns the
-// key of rank kc, which becomes the slot's threshold.
-__device__ uint64_t shrink_slot(uint64_t* slot, int cnt, int kc, uint32_t* hist) {
+// key of rank kc, which becomes the slot's threshold.  With deletion stamps
+// (death != null), keys of rows deleted before the query's view are dropped
+// first; when no more than kc visible keys remain they are all kept and the
+// returned key has distance +inf (no threshold).  Also returns the new count.
+struct Shrunk {
+    uint64_t kstar;
+    int n;
+};
+__device__ Shrunk shrink_slot(uint64_t* slot, int cnt, int kc, uint32_t* hist, const int32_t* death, int32_t view) {
     const int l = lane_id();
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    if (death) {
+        int base = 0;
+        for (int i0 = 0; i0 < cnt; i0 += WAVE) {
+            const int i = i0 + l;
+            const uint64_t k = i < cnt ? slot[i] : ~0ull;
+            const bool keep = i < cnt && death[key_index(k)] >= view;
+            const uint64_t m = ballot(keep);
+            if (keep) slot[base + __popcll(m & lanemask_lt())] = k;
+            base += __popcll(m);
+        }
+        cnt = base;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        if (cnt <= kc) return Shrunk{pack_key(INFINITY, -1), cnt};
+    }
     uint64_t kstar = wave_select(
         [&](auto f) {
             for (int i = l; i < cnt; i += WAVE) f(slot[i]);
@@ -294,7 +315,7 @@ __device__ uint64_t shrink_slot(uint64_t* slot, int cnt, int kc, uint32_t* hist)
         base += __popcll(m);
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    return kstar;
+    return Shrunk{kstar, kc};
 }
 
 // ---------------------------------------------------------------------------
@@ -320,12 +341,23 @@ struct TileArgs {
     int kc;
     const float* tau0;
     int64_t tau0_stride;
+    const int32_t* death;
+    const int32_t* views;
+    int32_t view;
     int MB, S, tiles_per_split, tile_lo, tile_hi, cap;
     uint64_t* slots;
     int32_t* counts;
 };
 
-template <int P>
+// Deletion visibility: key j exists for a request with view v iff it was not
+// deleted by one of the first v commits.
+__device__ __forceinline__ bool key_visible(const int32_t* death, int64_t j, int32_t view) {
+    return !death || death[j] >= view;
+}
+
+// VIS: the corpus carries deletion stamps (serving); a separate instantiation
+// so that the plain search keeps the visibility code out of its registers.
+template <int P, bool VIS>
 __global__ __launch_bounds__(TileGeom<P>::THREADS) __attribute__((amdgpu_waves_per_eu(TileGeom<P>::WPE, TileGeom<P>::WPE))) void knn_tile(TileArgs a) {
     constexpr int QB = TileGeom<P>::QB;
     constexpr int TILE_WAVES = TileGeom<P>::WAVES;
@@ -370,7 +402,8 @@ __global__ __launch_bounds__(TileGeom<P>::THREADS) __attribute__((amdgpu_waves_p
     const int sq_e8 = (P == ATSNE_PREC_FP8_E4M3 && qvalid) ? e8m0_of(a.scales[self]) : 127;
     uint64_t* myslot = a.slots + ((size_t)(qvalid ? mq : 0) * a.S + split) * (size_t)a.cap;
     float tau = -INFINITY;
-    if (qvalid) {
+    const int32_t* death = VIS ? a.death : nullptr;
+    if (qvalid && key_visible(death, self, a.views ? a.views[mq] : a.view)) {
         tau = INFINITY;
         if (a.tau0) {
             // reverse mode: only keys that may beat the row's farthest
@@ -378,7 +411,8 @@ __global__ __launch_bounds__(TileGeom<P>::THREADS) __attribute__((amdgpu_waves_p
             const float nq = a.norms[self];
             const float nmax = nl > 0 ? a.pmax[nl - 1] : 0.0f;
             const float dmax = a.tau0[mq * a.tau0_stride];
-            tau = dmax - nq + fp32_contraction_bound(a.Dp, nq, nmax, dmax) * 2.0f + 1e-30f;
+            tau = dmax > -INFINITY ? dmax - nq + fp32_contraction_bound(a.Dp, nq, nmax, dmax) * 2.0f + 1e-30f
+                                   : -INFINITY;  // a row with no neighbour left takes none
         }
     }
     // smallest key bound of the wave's queries: tiles below it need no range checks
@@ -482,10 +516,11 @@ __global__ __launch_bounds__(TileGeom<P>::THREADS) __attribute__((amdgpu_waves_p
                 int cnt_q = __shfl(count, q, WAVE);
                 int kc_q = __shfl(kcq, q, WAVE);
                 uint64_t* sq = a.slots + ((size_t)((int64_t)qb * QB + 32 * w + q) * a.S + split) * (size_t)a.cap;
-                uint64_t kstar = shrink_slot(sq, cnt_q, kc_q, hist);
+                const int32_t v_q = a.views ? a.views[(int64_t)qb * QB + 32 * w + q] : a.view;
+                const Shrunk sh = shrink_slot(sq, cnt_q, kc_q, hist, death, v_q);
                 if ((l & 31) == q) {
-                    count = kc_q;
-                    tau = fminf(tau, key_dist(kstar));
+                    count = sh.n;
+                    tau = fminf(tau, key_dist(sh.kstar));
                 }
             }
         }
@@ -579,8 +614,9 @@ __global__ __launch_bounds__(TileGeom<P>::THREADS) __attribute__((amdgpu_waves_p
             int cnt_q = __shfl(count, q, WAVE);
             int kc_q = __shfl(kcq, q, WAVE);
             uint64_t* sq = a.slots + ((size_t)((int64_t)qb * QB + 32 * w + q) * a.S + split) * (size_t)a.cap;
-            (void)shrink_slot(sq, cnt_q, kc_q, hist);
-            if ((l & 31) == q) count = kc_q;
+            const int32_t v_q = a.views ? a.views[(int64_t)qb * QB + 32 * w + q] : a.view;
+            const Shrunk sh = shrink_slot(sq, cnt_q, kc_q, hist, death, v_q);
+            if ((l & 31) == q) count = sh.n;
         }
     }
     if (qvalid && l < 32) a.counts[mq * a.S + split] = count;
@@ -714,6 +750,9 @@ struct SelArgs {
     const int32_t* kcs;
     int kc;
     int S, cap;
+    const int32_t* death;
+    const int32_t* views;
+    int32_t view;
     const uint64_t* slots;
     const int32_t* counts;
     int32_t* out_idx;
@@ -767,14 +806,28 @@ __global__ __launch_bounds__(64) void knn_select(SelArgs a, int kcap) {
     int32_t* out_idx = a.out_idx + m * a.out_stride;
     float* out_d2 = a.out_d2 + m * a.out_stride;
 
+    // with deletion stamps, slots can still hold keys of rows deleted before
+    // the row's view (those appended after the slot's last shrink): skip them
+    const int32_t vq = a.views ? a.views[m] : a.view;
     int total = 0;
-    for (int s = 0; s < a.S; ++s) total += cnt[s];
+    if (!a.death) {
+        for (int s = 0; s < a.S; ++s) total += cnt[s];
+    } else {
+        for (int s = 0; s < a.S; ++s) {
+            const uint64_t* sl = base + (size_t)s * a.cap;
+            for (int i0 = 0; i0 < cnt[s]; i0 += WAVE)
+                total += __popcll(ballot(i0 + l < cnt[s] && a.death[key_index(sl[i0 + l])] >= vq));
+        }
+    }
     const int take = min(kc, total);
     auto each = [&](auto f) {
         for (int s = 0; s < a.S; ++s) {
             const uint64_t* sl = base + (size_t)s * a.cap;
             const int c = cnt[s];
-            for (int i = l; i < c; i += WAVE) f(sl[i]);
+            for (int i = l; i < c; i += WAVE) {
+                const uint64_t key = sl[i];
+                if (!a.death || a.death[key_index(key)] >= vq) f(key);
+            }
         }
     };
     const uint64_t kstar = union_threshold(each, take, total, hist);
@@ -864,6 +917,7 @@ __global__ __launch_bounds__(256) void knn_scan(SelArgs a, int keep_extra, int32
         const int64_t q = load_qid(a.qids, a.m0, m);
         const int64_t nl = a.nlims ? (int64_t)a.nlims[m] : a.nlim;
         const int k = a.ks ? a.ks[m] : a.k;
+        const int32_t vq = a.views ? a.views[m] : a.view;
         const int keep = min(k + keep_extra, SCAN_REGION - 24);
         int32_t* out_idx = a.out_idx + m * a.out_stride;
         float* out_d2 = a.out_d2 + m * a.out_stride;
@@ -890,7 +944,8 @@ __global__ __launch_bounds__(256) void knn_scan(SelArgs a, int keep_extra, int32
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int64_t j = j0 + 4 * u;
-                const bool pass = j < nl && j != q && (strict ? (dj[u] < tau) : (dj[u] <= tau));
+                const bool pass = j < nl && j != q && key_visible(a.death, j, vq) &&
+                                  (strict ? (dj[u] < tau) : (dj[u] <= tau));
                 if (pass) {
                     if (l == 0) reg[cnt] = pack_key(dj[u], (int32_t)j);
                     ++cnt;
@@ -956,7 +1011,10 @@ __global__ __launch_bounds__(256) void knn_scan(SelArgs a, int keep_extra, int32
 // knn_reverse_merge: one wave per resident row.  Its candidates are new rows
 // whose approximate distance may beat the row's farthest neighbour; the exact
 // FP32 distance decides (Eq. 13, strict), and the survivors are merged into
-// the row's list, keeping its k best by (d, j).
+// the row's list, keeping its best by (d, j).  A list may hold absent entries
+// (index -1, distance +inf) at its tail after deletions (Sec. 5.3): Eq. 13
+// then works on the np present entries, whose farthest is d_max and is
+// evicted, so a merge never changes the number of present entries.
 struct RevArgs {
     SelArgs s;
     int32_t* res_idx;
@@ -980,6 +1038,7 @@ __global__ __launch_bounds__(64) void knn_reverse_merge(RevArgs r) {
     if (m >= a.M) return;
     const int64_t q = load_qid(a.qids, a.m0, m);
     const int k = a.k;
+    if (!key_visible(a.death, q, a.view)) return;
     const int32_t* cnt = a.counts + m * a.S;
     int total = 0;
     for (int s = 0; s < a.S; ++s) total += cnt[s];
@@ -996,6 +1055,9 @@ __global__ __launch_bounds__(64) void knn_reverse_merge(RevArgs r) {
     const uint64_t kstar = union_threshold(each, take, total, hist);
     int32_t* ridx = r.res_idx + q * r.res_stride;
     float* rd2 = r.res_d2 + q * r.res_stride;
+    int np = 0;
+    for (int i0 = 0; i0 < k; i0 += WAVE) np += __popcll(ballot(i0 + l < k && ridx[i0 + l] >= 0));
+    if (np == 0) return;
     if (l == 0) ncand = 0;
     wave_sync();
     each([&](uint64_t key) {
@@ -1008,8 +1070,8 @@ __global__ __launch_bounds__(64) void knn_reverse_merge(RevArgs r) {
     const int nc = ncand;
     const float* xq = a.X + q * a.ld;
     direct_distances(a.X, a.ld, a.D, xq, nc, cj + k, cd + k);
-    const float dmax = rd2[k - 1];
-    // keep the new keys strictly closer than the farthest neighbour
+    const float dmax = rd2[np - 1];
+    // keep the new keys strictly closer than the farthest present neighbour
     int c = 0;
     for (int i0 = 0; i0 < nc; i0 += WAVE) {
         const int i = i0 + l;
@@ -1027,12 +1089,27 @@ __global__ __launch_bounds__(64) void knn_reverse_merge(RevArgs r) {
         wave_sync();
     }
     if (c == 0) return;
-    for (int i = l; i < k; i += WAVE) {
+    if (np < k) {
+        // survivors move down next to the present entries (dst < src, so a
+        // chunk never overwrites a later chunk's unread entries)
+        for (int i0 = 0; i0 < c; i0 += WAVE) {
+            const int i = i0 + l;
+            const int32_t jj = i < c ? cj[k + i] : 0;
+            const float dv = i < c ? cd[k + i] : 0.f;
+            wave_sync();
+            if (i < c) {
+                cj[np + i] = jj;
+                cd[np + i] = dv;
+            }
+            wave_sync();
+        }
+    }
+    for (int i = l; i < np; i += WAVE) {
         cj[i] = ridx[i];
         cd[i] = rd2[i];
     }
     wave_sync();
-    finalize_row(a.X, a.ld, a.D, xq, k + c, k, cj, cd, sorted, dd, ridx, rd2,
+    finalize_row(a.X, a.ld, a.D, xq, np + c, np, cj, cd, sorted, dd, ridx, rd2,
                  r.res_flags ? r.res_flags + q : nullptr, 0);
     if (l == 0) {
         const int p = atomicAdd(r.n_changed, 1);
@@ -1179,6 +1256,9 @@ static atsne_status launch_tile(const Corpus& c, const Batch& b, const SearchPla
     t.kc = b.kc;
     t.tau0 = b.tau0;
     t.tau0_stride = b.tau0_stride;
+    t.death = c.death;
+    t.views = b.views;
+    t.view = b.view;
     t.MB = (int)ceil_div(b.M, TileGeom<P>::QB);
     t.S = p.S;
     t.tiles_per_split = p.tiles_per_split;
@@ -1188,7 +1268,16 @@ static atsne_status launch_tile(const Corpus& c, const Batch& b, const SearchPla
     t.slots = w.slots;
     t.counts = w.counts;
     ProfScope ps_(b.tau0 ? "knn_tile_reverse" : "knn_tile", st);
-    knn_tile<P><<<dim3((unsigned)(t.MB * p.S)), dim3(TileGeom<P>::THREADS), 0, st>>>(t);
+    const dim3 grid((unsigned)(t.MB * p.S)), block(TileGeom<P>::THREADS);
+    if constexpr (P == ATSNE_PREC_FP32) {
+        if (c.death)
+            knn_tile<P, true><<<grid, block, 0, st>>>(t);
+        else
+            knn_tile<P, false><<<grid, block, 0, st>>>(t);
+    } else {
+        ATSNE_REQUIRE(!c.death, ATSNE_E_UNSUPPORTED, "deletion stamps need the FP32 corpus");
+        knn_tile<P, false><<<grid, block, 0, st>>>(t);
+    }
     ATSNE_LAUNCH_CHECK();
     return ATSNE_OK;
 }
@@ -1225,6 +1314,9 @@ static SelArgs sel_args(const Corpus& c, const Batch& b, const SearchPlan& p, co
     s.kc = b.kc;
     s.S = p.S;
     s.cap = p.cap;
+    s.death = c.death;
+    s.views = b.views;
+    s.view = b.view;
     s.slots = w.slots;
     s.counts = w.counts;
     s.out_idx = b.out_idx;

@@ -23,6 +23,9 @@ struct Corpus {
     float* norms = nullptr;
     float* scales = nullptr;
     float* pmax = nullptr;
+    // Optional per-row deletion stamps (serving): row j is visible to a
+    // request whose view is v iff death[j] >= v (INT32_MAX = never deleted).
+    const int32_t* death = nullptr;
 };
 
 size_t corpus_bytes(int prec, int64_t rows_cap, int32_t D);
@@ -47,6 +50,8 @@ struct Batch {
     int kc = 0;
     const float* tau0 = nullptr;  // reverse mode: per-row distance that candidates must beat
     int64_t tau0_stride = 0;      // element stride of tau0 (rows' d_max inside a neighbour table)
+    const int32_t* views = nullptr;  // per-row view for deletion visibility; null: view
+    int32_t view = 0;
     int32_t* out_idx = nullptr;
     float* out_d2 = nullptr;
     uint8_t* out_flags = nullptr;
@@ -82,5 +87,17 @@ atsne_status knn_reverse(const Corpus& c, const Batch& b, const SearchPlan& p, i
 atsne_status calibrate_table(const float* d2, int64_t stride, const int32_t* row_ids, const int32_t* n_rows_dev,
                              int64_t n_rows, int k, float mu, float tol, int max_iter, float* P, float* beta,
                              float* perp, uint8_t* flags, hipStream_t st);
+
+// Serving-loop data manipulation (Sec. 5.3); resident lists have k entries
+// per row, present entries first, absent ones (index -1, +inf) last.
+atsne_status serve_fill_death(int32_t* death, int64_t n, hipStream_t st);
+atsne_status serve_mark_deleted(int32_t* death, const int32_t* ids, int64_t M, int32_t c, hipStream_t st);
+atsne_status serve_purge_deleted(int32_t* res_idx, float* res_d2, float* res_P, float* res_beta, uint8_t* res_flags,
+                                 int k, int64_t n_rows, const int32_t* death, int32_t c, int32_t* changed,
+                                 int32_t* n_changed, hipStream_t st);
+atsne_status serve_farthest(const int32_t* res_idx, const float* res_d2, int k, int64_t n_rows, float* dmax,
+                            hipStream_t st);
+atsne_status serve_state(const int32_t* res_idx, int k, int64_t n_rows, const int32_t* death, float* rho,
+                         uint8_t* alive, hipStream_t st);
 
 }  // namespace atsne

@@ -1,24 +1,32 @@
 // Serving loop for the steerable, progressive use of the similarity path:
-// streamed point insertion (Sec. 5.3, Eq. 13) and exact refinement of user
-// selections (Sec. 4.3, Sec. 5.1) against a device-resident corpus.
+// streamed point insertion (Sec. 5.3, Eq. 13), point deletion (Sec. 5.3) and
+// exact refinement of user selections (Sec. 4.3, Sec. 5.1) against a
+// device-resident corpus.  Inserting new points and deleting the oldest ones
+// is the sliding-window stream of Sec. 8.
 //
 // Continuous batching with iteration-level scheduling: a worker thread admits
 // queued requests while request slots and the HBM budget allow, then packs
 // row segments from every admitted request into one batched kNN launch (each
 // row carries its own corpus id, corpus prefix, k and k_cand).  Two batch
 // streams keep consecutive launches overlapped on the device; requests join
-// and leave between launches.  Inserts commit in arrival order on a commit
-// stream: their rows enter the resident neighbour table, the Eq. 13 reverse
-// merge updates every resident row that a new point beats, and the changed
-// rows are re-calibrated, all without a host synchronisation.
+// and leave between launches.  Inserts and deletes are commits, applied in
+// arrival order on a commit stream without a host synchronisation: an
+// insert's rows enter the resident neighbour table, the Eq. 13 reverse merge
+// updates every resident row that a new point beats, and the changed rows are
+// re-calibrated; a delete removes its points from every resident list (no
+// replacement: the row's precision falls by 1/K per removed neighbour) and
+// re-calibrates the rows it changed.
 //
-// Determinism: a request's rows search exactly the corpus prefix that
-// existed when it was submitted (its epoch), every row's arithmetic is
-// independent of the rows it shares a launch with, and the FP32 error bound
-// uses the prefix maximum of the norms, so a request's result is bitwise the
-// same alone or in any mix.
+// Determinism: every request carries a view, the number of commits submitted
+// before it.  Its rows search exactly the corpus that view defines (the rows
+// reserved before it, minus the rows deleted by earlier commits: a deleted
+// row keeps its storage and carries the index of the deleting commit), every
+// row's arithmetic is independent of the rows it shares a launch with, and
+// the FP32 error bound uses the prefix maximum of the norms, so a request's
+// result is bitwise the same alone or in any mix.
 #include <algorithm>
 #include <atomic>
+#include <climits>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -92,8 +100,8 @@ enum ReqState { PENDING, ADMITTED, FORWARD_DONE, FINISHING, DONE };
 
 struct Request {
     uint64_t id = 0;
-    int kind = 0;  // 0 insert, 1 refine
-    uint64_t epoch = 0;
+    int kind = 0;  // 0 insert, 1 refine, 2 delete
+    uint64_t epoch = 0;  // view: commits submitted before it (inserts/deletes: own commit index)
     int64_t n = 0;
     int k = 0, kc = 0;
     float mu = 0.f;
@@ -131,7 +139,7 @@ struct BatchSlot {
     std::vector<Seg> segs;
     void* ws = nullptr;
     size_t ws_bytes = 0;
-    int32_t* d_desc = nullptr;  // qids | nlims | ks | kcs, each max_rows
+    int32_t* d_desc = nullptr;  // qids | nlims | ks | kcs | views, each max_rows
     int32_t* h_desc = nullptr;  // pinned staging
     int32_t* b_idx = nullptr;
     float* b_d2 = nullptr;
@@ -160,7 +168,11 @@ struct atsne_server {
     float* res_P = nullptr;
     float* res_beta = nullptr;
     uint8_t* res_flags = nullptr;
+    float* res_dmax = nullptr;  // farthest present neighbour (Eq. 13 threshold)
+    int32_t* death = nullptr;   // per row: index of the deleting commit, INT_MAX if alive
+    int32_t* del_ids = nullptr;  // device staging of a delete's ids
     void* res_mem = nullptr;
+    std::vector<int32_t> h_death;  // host copy of death
 
     hipStream_t s_copy = nullptr, s_commit = nullptr, s_finish = nullptr;
     atsne::BatchSlot slot[2];
@@ -175,8 +187,8 @@ struct atsne_server {
     std::vector<atsne::Request*> active;
     std::map<uint64_t, atsne::Request*> all;
     uint64_t next_id = 1;
-    uint64_t inserts_submitted = 0, next_commit = 0;
-    int64_t n_reserved = 0, n_committed = 0;
+    uint64_t commits_submitted = 0, next_commit = 0;
+    int64_t n_reserved = 0, n_committed = 0, n_deleted = 0;
     bool stop = false;
     std::thread worker;
     atsne_serve_stats stats{};
@@ -203,8 +215,8 @@ size_t request_bytes(const Request& r) {
     a.take<float>(r.n * r.k);
     a.take<float>(r.n);
     a.take<uint8_t>(r.n);
-    if (r.kind == 0) {
-        a.take<int32_t>(std::max<int64_t>(r.row0, 1));
+    if (r.kind != 1) {
+        a.take<int32_t>(std::max<int64_t>(r.kind == 0 ? r.row0 : r.nlim, 1));
         a.take<int32_t>(1);
     }
     return a.used;
@@ -218,8 +230,8 @@ void carve_request(Request& r) {
     r.P = a.take<float>(r.n * r.k);
     r.beta = a.take<float>(r.n);
     r.flags = a.take<uint8_t>(r.n);
-    if (r.kind == 0) {
-        r.changed = a.take<int32_t>(std::max<int64_t>(r.row0, 1));
+    if (r.kind != 1) {
+        r.changed = a.take<int32_t>(std::max<int64_t>(r.kind == 0 ? r.row0 : r.nlim, 1));
         r.n_changed_dev = a.take<int32_t>(1);
     }
 }
@@ -231,6 +243,7 @@ atsne_status launch_batch(atsne_server* s, BatchSlot& b, std::vector<Seg>& segs,
     int32_t* hn = hq + R;
     int32_t* hk = hn + R;
     int32_t* hc = hk + R;
+    int32_t* hv = hc + R;
     int64_t key_hi = 0;
     for (const Seg& g : segs) {
         for (int64_t i = 0; i < g.n; ++i) {
@@ -239,10 +252,11 @@ atsne_status launch_batch(atsne_server* s, BatchSlot& b, std::vector<Seg>& segs,
             hn[g.b0 + i] = (int32_t)g.r->nlim;
             hk[g.b0 + i] = g.r->k;
             hc[g.b0 + i] = g.r->kc;
+            hv[g.b0 + i] = (int32_t)g.r->epoch;
         }
         key_hi = std::max(key_hi, g.r->nlim);
     }
-    ATSNE_HIP(hipMemcpyAsync(b.d_desc, b.h_desc, sizeof(int32_t) * 4 * R, hipMemcpyHostToDevice, b.st));
+    ATSNE_HIP(hipMemcpyAsync(b.d_desc, b.h_desc, sizeof(int32_t) * 5 * R, hipMemcpyHostToDevice, b.st));
     const int s_fit = 64;
     SearchPlan p = plan_search(ATSNE_PREC_FP32, rows, 0, key_hi, s->kmax, s->kcmax, s_fit);
     while (p.ws_bytes > b.ws_bytes && p.S > 1) p = plan_search(ATSNE_PREC_FP32, rows, 0, key_hi, s->kmax, s->kcmax, p.S - 1);
@@ -253,6 +267,7 @@ atsne_status launch_batch(atsne_server* s, BatchSlot& b, std::vector<Seg>& segs,
     bt.nlims = b.d_desc + R;
     bt.ks = b.d_desc + 2 * R;
     bt.kcs = b.d_desc + 3 * R;
+    bt.views = b.d_desc + 4 * R;
     bt.k = s->kmax;
     bt.kc = s->kcmax;
     bt.nlim = key_hi;
@@ -305,9 +320,11 @@ atsne_status commit_insert(atsne_server* s, Request& r) {
     ATSNE_HIP(hipMemcpyAsync(s->res_flags + r0, r.flags, B, hipMemcpyDeviceToDevice, st));
     ATSNE_TRY(calibrate_table(s->res_d2 + r0 * K, K, nullptr, nullptr, B, K, s->mu0, 1e-5f, 200, s->res_P + r0 * K,
                               s->res_beta + r0, nullptr, s->res_flags + r0, st));
-    // 2. Eq. 13 over the residents that existed before this insert
+    // 2. Eq. 13 over the residents that existed before this insert; the
+    // threshold of a row is its farthest present neighbour
     ATSNE_HIP(hipMemsetAsync(r.n_changed_dev, 0, sizeof(int32_t), st));
     if (r0 > 0) {
+        ATSNE_TRY(serve_farthest(s->res_idx, s->res_d2, K, r0, s->res_dmax, st));
         SearchPlan p = plan_search(ATSNE_PREC_FP32, r0, r0, r0 + B, K, K);
         while (p.ws_bytes > s->rev_ws_bytes && p.S > 1) p = plan_search(ATSNE_PREC_FP32, r0, r0, r0 + B, K, K, p.S - 1);
         ATSNE_REQUIRE(p.ws_bytes <= s->rev_ws_bytes, ATSNE_E_NOMEM, "reverse workspace too small");
@@ -318,8 +335,9 @@ atsne_status commit_insert(atsne_server* s, Request& r) {
         bt.key_lo = r0;
         bt.k = K;
         bt.kc = K;
-        bt.tau0 = s->res_d2 + (K - 1);
-        bt.tau0_stride = K;
+        bt.tau0 = s->res_dmax;
+        bt.tau0_stride = 1;
+        bt.view = (int32_t)r.epoch;
         ATSNE_TRY(knn_reverse(s->corpus, bt, p, s->res_idx, s->res_d2, s->res_flags, K, r.changed, r.n_changed_dev,
                               s->rev_ws, st));
         // 3. re-calibrate the changed rows in place (count stays on the device)
@@ -330,6 +348,22 @@ atsne_status commit_insert(atsne_server* s, Request& r) {
     ATSNE_HIP(hipMemcpyAsync(r.P, s->res_P + r0 * K, sizeof(float) * B * K, hipMemcpyDeviceToDevice, st));
     ATSNE_HIP(hipMemcpyAsync(r.beta, s->res_beta + r0, sizeof(float) * B, hipMemcpyDeviceToDevice, st));
     ATSNE_HIP(hipMemcpyAsync(r.flags, s->res_flags + r0, B, hipMemcpyDeviceToDevice, st));
+    ATSNE_HIP(hipMemcpyAsync(r.n_changed_host, r.n_changed_dev, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    ATSNE_HIP(hipEventRecord(r.fin, st));
+    return ATSNE_OK;
+}
+
+// Commit a delete (in commit order, on the commit stream): every resident row
+// reserved before it drops the deleted points, the deleted rows are emptied,
+// and the changed rows are re-calibrated over their remaining neighbours.
+atsne_status commit_delete(atsne_server* s, Request& r) {
+    hipStream_t st = s->s_commit;
+    const int K = s->K0;
+    ATSNE_HIP(hipMemsetAsync(r.n_changed_dev, 0, sizeof(int32_t), st));
+    ATSNE_TRY(serve_purge_deleted(s->res_idx, s->res_d2, s->res_P, s->res_beta, s->res_flags, K, r.nlim, s->death,
+                                  (int32_t)r.epoch, r.changed, r.n_changed_dev, st));
+    ATSNE_TRY(calibrate_table(s->res_d2, K, r.changed, r.n_changed_dev, r.nlim, K, s->mu0, 1e-5f, 200, s->res_P,
+                              s->res_beta, nullptr, s->res_flags, st));
     ATSNE_HIP(hipMemcpyAsync(r.n_changed_host, r.n_changed_dev, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     ATSNE_HIP(hipEventRecord(r.fin, st));
     return ATSNE_OK;
@@ -354,7 +388,7 @@ void worker_loop(atsne_server* s) {
             if (!r->mem) break;  // wait for releases
             s->pending.pop_front();
             carve_request(*r);
-            r->state = ADMITTED;
+            r->state = r->kind == 2 ? FORWARD_DONE : ADMITTED;  // a delete searches nothing
             r->t_admit = now_ms(s->t0);
             (void)hipMemcpyAsync(r->row_ids, r->ids_host.data(), sizeof(int32_t) * r->n, hipMemcpyHostToDevice,
                                  s->s_copy);
@@ -406,7 +440,7 @@ void worker_loop(atsne_server* s) {
                 st = finish_refine(s, *r);
             } else {
                 if (r->epoch != s->next_commit) continue;
-                st = commit_insert(s, *r);
+                st = r->kind == 0 ? commit_insert(s, *r) : commit_delete(s, *r);
                 s->next_commit++;
             }
             if (st != ATSNE_OK) {
@@ -452,12 +486,13 @@ void fill_result(const Request& r, atsne_result* o) {
     o->k = r.k;
     o->perplexity = r.mu;
     o->row_ids = r.row_ids;
-    o->nbr_idx = r.nbr_idx;
-    o->nbr_d2 = r.nbr_d2;
-    o->P_cond = r.P;
-    o->beta = r.beta;
-    o->flags = r.flags;
-    o->n_changed = (r.kind == 0 && r.n_changed_host) ? *r.n_changed_host : 0;
+    const bool rows = r.kind != 2;
+    o->nbr_idx = rows ? r.nbr_idx : nullptr;
+    o->nbr_d2 = rows ? r.nbr_d2 : nullptr;
+    o->P_cond = rows ? r.P : nullptr;
+    o->beta = rows ? r.beta : nullptr;
+    o->flags = rows ? r.flags : nullptr;
+    o->n_changed = (r.kind != 1 && r.n_changed_host) ? *r.n_changed_host : 0;
     o->changed = r.changed;
     o->t_submit_ms = r.t_submit;
     o->t_admit_ms = r.t_admit;
@@ -524,6 +559,9 @@ extern "C" atsne_status atsne_serve_create(const atsne_serve_config* cfg, const 
         a.take<float>(cap * K0);
         a.take<float>(cap);
         a.take<uint8_t>(cap);
+        a.take<float>(cap);
+        a.take<int32_t>(cap);
+        a.take<int32_t>(cap);
         if ((st = alloc_dev(&s->res_mem, a.used)) != ATSNE_OK) return fail(st);
         Arena b(s->res_mem, a.used);
         s->res_idx = b.take<int32_t>(cap * K0);
@@ -531,6 +569,11 @@ extern "C" atsne_status atsne_serve_create(const atsne_serve_config* cfg, const 
         s->res_P = b.take<float>(cap * K0);
         s->res_beta = b.take<float>(cap);
         s->res_flags = b.take<uint8_t>(cap);
+        s->res_dmax = b.take<float>(cap);
+        s->death = b.take<int32_t>(cap);
+        s->del_ids = b.take<int32_t>(cap);
+        s->corpus.death = s->death;
+        s->h_death.assign(cap, INT_MAX);
     }
     if (hipStreamCreateWithFlags(&s->s_copy, hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&s->s_commit, hipStreamNonBlocking) != hipSuccess ||
@@ -545,11 +588,11 @@ extern "C" atsne_status atsne_serve_create(const atsne_serve_config* cfg, const 
         for (auto& b : s->slot) {
             b.ws_bytes = p.ws_bytes;
             if ((st = alloc_dev(&b.ws, b.ws_bytes)) != ATSNE_OK) return fail(st);
-            if ((st = alloc_dev((void**)&b.d_desc, sizeof(int32_t) * 4 * R)) != ATSNE_OK) return fail(st);
+            if ((st = alloc_dev((void**)&b.d_desc, sizeof(int32_t) * 5 * R)) != ATSNE_OK) return fail(st);
             if ((st = alloc_dev((void**)&b.b_idx, sizeof(int32_t) * R * s->kmax)) != ATSNE_OK) return fail(st);
             if ((st = alloc_dev((void**)&b.b_d2, sizeof(float) * R * s->kmax)) != ATSNE_OK) return fail(st);
             if ((st = alloc_dev((void**)&b.b_flags, R)) != ATSNE_OK) return fail(st);
-            if (hipHostMalloc((void**)&b.h_desc, sizeof(int32_t) * 4 * R, hipHostMallocDefault) != hipSuccess ||
+            if (hipHostMalloc((void**)&b.h_desc, sizeof(int32_t) * 5 * R, hipHostMallocDefault) != hipSuccess ||
                 hipStreamCreateWithFlags(&b.st, hipStreamNonBlocking) != hipSuccess ||
                 hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) != hipSuccess) {
                 set_error("batch slot setup failed");
@@ -570,6 +613,7 @@ extern "C" atsne_status atsne_serve_create(const atsne_serve_config* cfg, const 
         set_error("corpus copy failed");
         return fail(ATSNE_E_HIP);
     }
+    if ((st = serve_fill_death(s->death, cap, cs)) != ATSNE_OK) return fail(st);
     if ((st = corpus_prep(s->corpus, 0, cap, N, cs)) != ATSNE_OK) return fail(st);
     {
         SearchPlan p = plan_search(ATSNE_PREC_FP32, std::min<int64_t>(N, 65536), 0, N, K0, s->kc0);
@@ -650,7 +694,7 @@ extern "C" atsne_status atsne_serve_submit_insert(atsne_server* s, const float* 
     {
         std::lock_guard<std::mutex> lk(s->mu);
         r->id = s->next_id++;
-        r->epoch = s->inserts_submitted++;
+        r->epoch = s->commits_submitted++;
         r->t_submit = now_ms(s->t0);
         s->n_reserved += B;
         s->stats.corpus_rows = s->n_reserved;
@@ -677,22 +721,25 @@ extern "C" atsne_status atsne_serve_submit_refine(atsne_server* s, const int32_t
     r->k = k;
     r->kc = k + std::max(32, k / 2);
     r->mu = perplexity;
+    int64_t n_alive;
     {
         std::lock_guard<std::mutex> lk(s->mu);
         r->nlim = s->n_reserved;
-        r->epoch = s->inserts_submitted;
+        r->epoch = s->commits_submitted;
+        n_alive = s->n_reserved - s->n_deleted;
     }
-    if (!(perplexity < k) || k > r->nlim - 1) {
+    if (!(perplexity < k) || k > n_alive - 1) {
         delete r;
-        set_error("k=%d out of range for the corpus", k);
+        set_error("k=%d out of range for a corpus of %lld live points", k, (long long)n_alive);
         return ATSNE_E_K_RANGE;
     }
-    r->kc = (int)std::min<int64_t>(r->kc, r->nlim - 1);
+    r->kc = (int)std::min<int64_t>(r->kc, n_alive - 1);
     r->ids_host.assign(ids_host, ids_host + M);
+    // deletes are submitted under submit_mu too, so h_death is stable here
     for (int32_t v : r->ids_host)
-        if (v < 0 || v >= r->nlim) {
+        if (v < 0 || v >= r->nlim || s->h_death[v] != INT_MAX) {
             delete r;
-            set_error("refine id %d outside the corpus [0, %lld)", v, (long long)r->nlim);
+            set_error("refine id %d is not a live point of the corpus [0, %lld)", v, (long long)r->nlim);
             return ATSNE_E_INVALID_ARG;
         }
     r->bytes = request_bytes(*r);
@@ -711,6 +758,89 @@ extern "C" atsne_status atsne_serve_submit_refine(atsne_server* s, const int32_t
         ATSNE_REQUIRE(!s->stop, ATSNE_E_INVALID_ARG, "server is shutting down");
         r->id = s->next_id++;
         r->t_submit = now_ms(s->t0);
+        s->stats.submitted++;
+        s->all[r->id] = r;
+        s->pending.push_back(r);
+        *req_id = r->id;
+    }
+    s->cv.notify_all();
+    return ATSNE_OK;
+}
+
+extern "C" atsne_status atsne_serve_submit_delete(atsne_server* s, const int32_t* ids_host, int32_t M,
+                                                  uint64_t* req_id) {
+    clear_error();
+    ATSNE_REQUIRE(s && ids_host && req_id && M >= 1, ATSNE_E_INVALID_ARG, "bad arguments");
+    std::lock_guard<std::mutex> sl(s->submit_mu);
+    auto* r = new Request();
+    r->kind = 2;
+    r->n = M;
+    r->k = 0;
+    r->mu = s->mu0;
+    int64_t n_alive;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->stop) {
+            delete r;
+            set_error("server is shutting down");
+            return ATSNE_E_INVALID_ARG;
+        }
+        r->nlim = s->n_reserved;
+        n_alive = s->n_reserved - s->n_deleted;
+    }
+    if (n_alive - M < (int64_t)s->K0 + 1) {
+        delete r;
+        set_error("deleting %d of %lld live points leaves fewer than k+1 = %d", M, (long long)n_alive, s->K0 + 1);
+        return ATSNE_E_K_RANGE;
+    }
+    r->ids_host.assign(ids_host, ids_host + M);
+    {
+        std::vector<int32_t> sorted(r->ids_host);
+        std::sort(sorted.begin(), sorted.end());
+        for (size_t i = 0; i < sorted.size(); ++i) {
+            const int32_t v = sorted[i];
+            if (v < 0 || v >= r->nlim || s->h_death[v] != INT_MAX || (i > 0 && sorted[i - 1] == v)) {
+                delete r;
+                set_error("delete id %d is not a distinct live point of the corpus [0, %lld)", v, (long long)r->nlim);
+                return ATSNE_E_INVALID_ARG;
+            }
+        }
+    }
+    r->bytes = request_bytes(*r);
+    if (r->bytes > s->arena.cap()) {
+        delete r;
+        set_error("request needs more than the HBM budget");
+        return ATSNE_E_NOMEM;
+    }
+    if (hipEventCreateWithFlags(&r->fin, hipEventDisableTiming) != hipSuccess ||
+        hipHostMalloc((void**)&r->n_changed_host, sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+        free_request(s, r);
+        set_error("delete staging failed");
+        return ATSNE_E_HIP;
+    }
+    *r->n_changed_host = 0;
+    // The deletion stamp is written now: requests submitted later never see
+    // these rows, earlier ones still do (their view is at most this index).
+    uint64_t c;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        c = s->commits_submitted;
+    }
+    if (hipMemcpyAsync(s->del_ids, r->ids_host.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice, s->s_copy) !=
+            hipSuccess ||
+        serve_mark_deleted(s->death, s->del_ids, M, (int32_t)c, s->s_copy) != ATSNE_OK ||
+        hipStreamSynchronize(s->s_copy) != hipSuccess) {
+        free_request(s, r);
+        set_error("delete staging failed");
+        return ATSNE_E_HIP;
+    }
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (int32_t v : r->ids_host) s->h_death[v] = (int32_t)c;
+        r->id = s->next_id++;
+        r->epoch = s->commits_submitted++;
+        r->t_submit = now_ms(s->t0);
+        s->n_deleted += M;
         s->stats.submitted++;
         s->all[r->id] = r;
         s->pending.push_back(r);
@@ -767,28 +897,33 @@ extern "C" atsne_status atsne_serve_stats_get(atsne_server* s, atsne_serve_stats
 }
 
 extern "C" atsne_status atsne_serve_snapshot(atsne_server* s, int64_t cap_rows, float* corpus, int32_t* nbr_idx,
-                                             float* nbr_d2, int64_t* n_rows, uint64_t* epoch) {
+                                             float* nbr_d2, float* P_cond, float* beta, float* rho,
+                                             uint8_t* alive, int64_t* n_rows, uint64_t* epoch) {
     clear_error();
     ATSNE_REQUIRE(s && n_rows && epoch, ATSNE_E_INVALID_ARG, "bad arguments");
     std::unique_lock<std::mutex> lk(s->mu);
-    // wait for every submitted insert to commit
+    // wait for every submitted commit to be applied
     s->cv.notify_all();
     s->cv_done.wait(lk, [&] {
-        if (s->next_commit != s->inserts_submitted) return false;
+        if (s->next_commit != s->commits_submitted) return false;
         for (Request* r : s->active)
-            if (r->kind == 0) return false;
+            if (r->kind != 1) return false;
         for (Request* r : s->pending)
-            if (r->kind == 0) return false;
+            if (r->kind != 1) return false;
         return true;
     });
     const int64_t n = s->n_committed;
     *n_rows = n;
-    *epoch = s->inserts_submitted;
+    *epoch = s->commits_submitted;
     ATSNE_REQUIRE(cap_rows >= n, ATSNE_E_NOMEM, "snapshot needs %lld rows", (long long)n);
     ATSNE_HIP(hipStreamSynchronize(s->s_commit));
     if (corpus) ATSNE_HIP(hipMemcpy(corpus, s->X, sizeof(float) * n * s->D, hipMemcpyDeviceToDevice));
     if (nbr_idx) ATSNE_HIP(hipMemcpy(nbr_idx, s->res_idx, sizeof(int32_t) * n * s->K0, hipMemcpyDeviceToDevice));
     if (nbr_d2) ATSNE_HIP(hipMemcpy(nbr_d2, s->res_d2, sizeof(float) * n * s->K0, hipMemcpyDeviceToDevice));
+    if (P_cond) ATSNE_HIP(hipMemcpy(P_cond, s->res_P, sizeof(float) * n * s->K0, hipMemcpyDeviceToDevice));
+    if (beta) ATSNE_HIP(hipMemcpy(beta, s->res_beta, sizeof(float) * n, hipMemcpyDeviceToDevice));
+    ATSNE_TRY(serve_state(s->res_idx, s->K0, n, s->death, rho, alive, s->s_commit));
+    ATSNE_HIP(hipStreamSynchronize(s->s_commit));
     return ATSNE_OK;
 }
 

@@ -17,6 +17,13 @@ numpy.random.Generator(PCG64(seed)).
   mixture_anisotropic N=1e6, D=128: 50 Gaussian clusters, centres ~ N(0, 16 I),
                       covariance Q diag(lambda) Q^T with lambda ~ U[0.1, 4] and
                       Q the sign-fixed QR factor of a Gaussian matrix.
+  activity_stream     stand-in for the sensor stream of Sec. 8 (52 readings
+                      every 100 ms, 24 labelled activities): a time-ordered
+                      sequence of activity segments (length ~ U[200, 900]
+                      readings, activity drawn uniformly from 24 centres ~
+                      N(0, 9 I)); within a segment each reading is the centre
+                      plus an AR(1) drift (coefficient 0.98, innovation
+                      N(0, 0.2^2 I)) plus N(0, 0.5^2 I) sensor noise.
 """
 from __future__ import annotations
 
@@ -82,6 +89,23 @@ def mixture_anisotropic(n: int = 1_000_000, d: int = 128, n_clusters: int = 50, 
         rows = np.nonzero(lab == m)[0]
         z = rng.normal(size=(rows.size, d))
         out[rows] = (centres[m] + (z * np.sqrt(lam)[None, :]) @ q.T).astype(np.float32)
+    return out
+
+
+def activity_stream(n: int = 12000, d: int = 52, n_activities: int = 24, seed: int = BASE_SEED + 5) -> np.ndarray:
+    """Time-ordered readings (row t is the reading at tick t)."""
+    rng = _rng(seed)
+    centres = rng.normal(0.0, 3.0, size=(n_activities, d))
+    out = np.empty((n, d), np.float32)
+    t = 0
+    drift = np.zeros(d)
+    while t < n:
+        length = int(rng.integers(200, 901))
+        act = int(rng.integers(0, n_activities))
+        for s in range(t, min(n, t + length)):
+            drift = 0.98 * drift + rng.normal(0.0, 0.2, size=d)
+            out[s] = centres[act] + drift + rng.normal(0.0, 0.5, size=d)
+        t += length
     return out
 
 

@@ -162,3 +162,173 @@ def test_serve_errors(A):
         s.insert(torch.zeros((200, 50), device="cuda"))  # capacity 600 rows
     assert e.value.status == A.E_NOMEM
     s.close()
+
+
+# ---------------------------------------------------------------------------
+# Deletion and the sliding window (Sec. 5.3, Sec. 8) against the FP64 model
+# ---------------------------------------------------------------------------
+from oracle import serve_model as SM  # noqa: E402
+
+
+def _run_ops(A, X0, mu0, ops, wait_each, capacity):
+    """ops: ('i', points) / ('d', ids) / ('r', ids, mu).  Returns (results, snapshot, stats)."""
+    s = A.Server(torch.from_numpy(X0).cuda(), mu0, capacity_rows=capacity)
+    rids, out = [], []
+    for op in ops:
+        if op[0] == "i":
+            rid = s.insert(torch.from_numpy(op[1]).cuda())
+        elif op[0] == "d":
+            rid = s.delete(op[1])
+        else:
+            rid = s.refine(op[1], op[2])
+        if wait_each:
+            out.append(s.wait(rid))
+            s.release(rid)
+        else:
+            rids.append(rid)
+    for rid in rids:
+        out.append(s.wait(rid))
+        s.release(rid)
+    snap = s.snapshot()
+    st = s.stats()
+    s.close()
+    return out, snap, st
+
+
+def _check_against_model(m, snap, results, ops, label):
+    X, idx, d2, P, beta, rho, alive = snap
+    n = m.n_rows()
+    assert X.shape[0] == n and np.array_equal(X, m.X)
+    assert np.array_equal(alive.astype(bool), m.alive), "%s: alive flags" % label
+    tie = np.zeros(n, bool)
+    tie[list(m.tie_rows)] = True
+    ok = ~tie
+    # same listed set per row (the order of near-equal distances inside a list
+    # may differ between FP32 and FP64), absent entries at the tail
+    gs, ms = np.sort(idx, axis=1), np.sort(m.idx, axis=1)
+    bad = np.flatnonzero(ok & (gs != ms).any(axis=1))
+    for i in bad[:3]:
+        say("    row %d: gpu %s / %s  model %s / %s" % (i, idx[i].tolist(), d2[i].tolist(), m.idx[i].tolist(),
+                                                     m.d2[i].tolist()))
+    assert bad.size == 0, "%s: listed sets differ in %d rows" % (label, bad.size)
+    assert np.array_equal(rho[ok], m.rho()[ok].astype(np.float32))
+    pres = idx >= 0
+    assert np.all(pres[:, :-1] >= pres[:, 1:]), "absent entries must trail"
+    dd = np.where(pres, d2, np.inf)
+    with np.errstate(invalid="ignore"):
+        assert np.all(np.diff(dd, axis=1)[pres[:, 1:]] >= 0), "listed distances not ascending"
+    # FP32 direct-difference distances of the listed points
+    td = parity.true_d2(m.X, np.arange(n), np.maximum(idx, 0))
+    e = np.abs(d2[pres].astype(np.float64) - td[pres])
+    assert np.all(e <= parity.D2_REL * td[pres] + 1e-30)
+    assert np.all(np.isinf(d2[~pres]))
+    # calibration over the listed neighbours, from the GPU's own distances
+    o_P, o_beta, o_fl = SM.calibrate_absent(d2.astype(np.float64), m.mu)
+    assert np.abs(P - o_P).max() <= parity.P_TOL, "%s: max |dP| %g" % (label, np.abs(P - o_P).max())
+    few = np.isfinite(d2).sum(axis=1) <= m.mu  # uniform over the listed neighbours (or empty)
+    assert np.all(beta[few] == 0.0)
+    say("    %s: %d rows (%d alive, %d with removed neighbours, %d tie rows)" % (
+        label, n, int(alive.sum()), int(((rho < 1) & (alive > 0)).sum()), int(tie.sum())))
+
+
+def _mixed_ops(X0, seed):
+    rng = np.random.default_rng(seed)
+    pts = datagen.mixture_isotropic(n=1200, d=X0.shape[1], seed=seed + 1)
+    ops, off = [], 0
+    n, alive = X0.shape[0], np.ones(X0.shape[0], bool)
+    for B, n_del, n_ref in [(64, 40, 300), (0, 400, 50), (300, 17, 0), (1, 1, 999), (500, 250, 20),
+                            (100, 0, 700), (0, 60, 0)]:
+        if B:
+            ops.append(("i", pts[off:off + B]))
+            off += B
+            alive = np.concatenate([alive, np.ones(B, bool)])
+        if n_del:
+            # a mix of old points and points of the last insert
+            ids = rng.choice(np.flatnonzero(alive), size=n_del, replace=False).astype(np.int32)
+            ops.append(("d", ids))
+            alive[ids] = False
+        if n_ref:
+            ids = rng.choice(np.flatnonzero(alive), size=n_ref, replace=False).astype(np.int32)
+            ops.append(("r", ids, [10.0, 30.0, 50.0][n_ref % 3]))
+    return ops
+
+
+def test_serve_delete_alone_vs_mix_and_model(A):
+    X0 = _corpus(n=2500, seed=35)
+    mu0 = 10.0
+    ops = _mixed_ops(X0, 8)
+    cap = X0.shape[0] + 1200
+    say("  serve+delete: %d requests, alone" % len(ops))
+    alone, snap_a, _ = _run_ops(A, X0, mu0, ops, True, cap)
+    say("  serve+delete: same requests in the mix")
+    mix, snap_m, st = _run_ops(A, X0, mu0, ops, False, cap)
+    say("    mix stats %s" % st)
+    for op, a, b in zip(ops, alone, mix):
+        assert a["status"] == 0 and b["status"] == 0 and a["epoch"] == b["epoch"]
+        if op[0] == "d":
+            assert a["kind"] == "delete" and sorted(a["changed"].tolist()) == sorted(b["changed"].tolist())
+        else:
+            _same(a, b, keys=("row_ids", "idx", "d2", "P", "beta", "flags"))
+    for x, y in zip(snap_a, snap_m):
+        assert np.array_equal(x, y)
+    # the FP64 model replays the commits; refines are checked on the live subset
+    m = SM.ResidentModel(X0, mu0)
+    for op, r in zip(ops, alone):
+        if op[0] == "i":
+            ch = m.insert(op[1])
+            got = np.sort(r["changed"])
+            tie = np.array([i in m.tie_rows for i in range(m.n_rows())])
+            assert np.array_equal(got[~tie[got]], ch[~tie[ch]]), "insert changed rows differ"
+        elif op[0] == "d":
+            ch = m.delete(op[1])
+            assert np.array_equal(np.sort(r["changed"]), ch), "delete changed rows differ"
+        else:
+            live = np.flatnonzero(m.alive)
+            pos = np.searchsorted(live, op[1]).astype(np.int32)
+            ref = _standalone(A, m.X[live], pos, op[2])
+            ref["idx"] = live[ref["idx"]].astype(np.int32)
+            _same(r, ref)
+    _check_against_model(m, snap_a, alone, ops, "final state")
+
+
+def test_serve_sliding_window(A):
+    """Stream readings through a window: each tick inserts the new readings
+    and deletes the ones that left the window (Sec. 8)."""
+    W, D, T, per_tick = 1500, 52, 120, 3
+    stream = datagen.activity_stream(n=W + T * per_tick, d=D, seed=41)
+    X0 = stream[:W]
+    ops = []
+    for t in range(T):
+        a = W + t * per_tick
+        ops.append(("i", stream[a:a + per_tick]))
+        ops.append(("d", np.arange(t * per_tick, (t + 1) * per_tick, dtype=np.int32)))
+    say("  sliding window W=%d, %d ticks of %d readings" % (W, T, per_tick))
+    res, snap, st = _run_ops(A, X0, 10.0, ops, False, stream.shape[0])
+    assert all(r["status"] == 0 for r in res)
+    m = SM.ResidentModel(X0, 10.0)
+    for op in ops:
+        (m.insert if op[0] == "i" else m.delete)(op[1])
+    assert int(m.alive.sum()) == W
+    _check_against_model(m, snap, res, ops, "window")
+    lat = np.array([r["t_complete_ms"] - r["t_submit_ms"] for r in res])
+    say("    commit latency p50 %.2f ms p99 %.2f ms" % (np.percentile(lat, 50), np.percentile(lat, 99)))
+
+
+def test_serve_delete_errors(A):
+    X = _corpus(n=300, seed=36)
+    s = A.Server(torch.from_numpy(X).cuda(), 10.0, capacity_rows=400)
+    rid = s.delete(np.array([3, 7], np.int32))
+    s.wait(rid)
+    s.release(rid)
+    for bad in ([3], [300], [-1], [5, 5]):  # deleted, outside, negative, duplicate
+        with pytest.raises(A.AtsneError):
+            s.delete(np.array(bad, np.int32))
+    with pytest.raises(A.AtsneError):
+        s.refine(np.array([0, 7], np.int32), 10.0)  # 7 was deleted
+    with pytest.raises(A.AtsneError) as e:
+        s.delete(np.arange(10, 280, dtype=np.int32))  # would leave fewer than K+1 live points
+    assert e.value.status == A.E_K_RANGE
+    r = s.wait(s.refine(np.array([0, 1], np.int32), 10.0))
+    assert r["status"] == 0 and not np.isin(r["idx"], [3, 7]).any()
+    s.release(r["req_id"])
+    s.close()
