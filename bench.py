@@ -182,6 +182,42 @@ def serve_load(A, torch, X, rate, n_req, n_warm, seed=5):
     }
 
 
+def window_stream(A, torch, W=6000, D=52, ticks=400, warm=40, mu=30.0, seed=41):
+    """Sliding window of Sec. 8 on a synthetic activity stream: the window
+    keeps the last W readings; each tick inserts the new reading and deletes
+    the one that left the window.  Ticks run closed-loop (submit insert and
+    delete, wait for both); tick latency = delete completion - insert
+    submission, against the stream's 100 ms reading period."""
+    from paper_1512_01655_amd import datagen
+
+    stream = datagen.activity_stream(n=W + ticks, d=D, seed=seed)
+    dev = torch.from_numpy(stream).cuda()
+    srv = A.Server(dev[:W].contiguous(), mu, capacity_rows=W + ticks + 1)
+    lat = []
+    t_first = None
+    for t in range(ticks):
+        if t == warm:
+            t_first = time.perf_counter()
+        ri = srv.insert(dev[W + t:W + t + 1])
+        rd = srv.delete(np.array([t], np.int32))
+        r1 = srv.wait(ri, fetch=False)
+        r2 = srv.wait(rd, fetch=False)
+        if r1["status"] != 0 or r2["status"] != 0:
+            raise RuntimeError("window tick %d failed" % t)
+        lat.append(r2["t_complete_ms"] - r1["t_submit_ms"])
+        srv.release(ri)
+        srv.release(rd)
+    span = time.perf_counter() - t_first
+    srv.close()
+    lm = np.array(lat[warm:])
+    return {
+        "window": W, "dims": D, "perplexity": mu, "ticks": ticks - warm, "warmup_ticks": warm,
+        "tick_p50_ms": round(float(np.percentile(lm, 50)), 3), "tick_p99_ms": round(float(np.percentile(lm, 99)), 3),
+        "ticks_per_s": round((ticks - warm) / span, 1), "reading_period_ms": 100.0,
+        "data": "synthetic activity stream (24 activities, AR(1) drift), 1 insert + 1 delete per tick",
+    }
+
+
 def cpu_baseline(X, mu, k, target_s):
     from oracle import oracle as O
 
@@ -287,6 +323,10 @@ def main():
         log("serve: Poisson stream at %.0f req/s ..." % a.serve_rate)
         line["serve"] = serve_load(A, torch, X, a.serve_rate, a.serve_requests + 10, 10)
         log("serve: p50 %.1f ms, p99 %.1f ms" % (line["serve"]["p50_ms"], line["serve"]["p99_ms"]))
+    if not a.no_serve:
+        log("window: sliding-window stream ...")
+        line["window"] = window_stream(A, torch)
+        log("window: tick p50 %.2f ms, p99 %.2f ms" % (line["window"]["tick_p50_ms"], line["window"]["tick_p99_ms"]))
     if not a.no_cpu_baseline:
         log("cpu baseline: timing the FP64 oracle on a bounded sample ...")
         line["cpu_baseline"] = cpu_baseline(X, mu, k, a.cpu_seconds)

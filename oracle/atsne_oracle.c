@@ -22,6 +22,10 @@
  *   - atsne_oracle_symmetrize: the joint p_ij = (p_{j|i} + p_{i|j}) / (2N) of
  *     Eq. 2, equivalently the split form of Eq. 10, as CSR with ascending
  *     columns.
+ *   - atsne_oracle_attractive: the attractive term of the gradient (Eq. 7)
+ *     over the sparse symmetric P, sum_j p_ij q_ij Z (y_i - y_j) with
+ *     q_ij Z = 1/(1 + |y_i - y_j|^2) (Eq. 5, Eq. 6), scaled per point by the
+ *     exaggeration of Sec. 4.3.
  *
  * Readings of the paper taken here (the paper is silent or literal-minded):
  *   - Eq. 8 writes the normaliser as a sum over all k != i; the sparse rows
@@ -30,6 +34,10 @@
  *   - Degenerate rows (the target perplexity is unreachable because m >= mu
  *     neighbours sit at the minimum distance, or all distances are equal) are
  *     flagged and given the limiting distribution.
+ *   - Selective exaggeration with exponential decay (Sec. 4.3) gives no
+ *     formula: point i refined at iteration t_ref has its attraction scaled
+ *     by 1 + (tau - 1) exp(-(t - t_ref)/decay), times the global early
+ *     exaggeration factor.
  *
  * Parity status: every function here is pinned by the CPU test suite
  * (exact-rational brute force, closed forms, invariants, metamorphic
@@ -416,6 +424,65 @@ int64_t atsne_oracle_symmetrize(const int64_t* in_ptr, const int32_t* in_col,
     for (int64_t i = 0; i < N; ++i) out_ptr[i + 1] += out_ptr[i];
     free(t);
     return nnz;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Attractive forces of the gradient (Eq. 5, Eq. 6, Eq. 7)                   */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Exaggeration multiplier of point i at iteration t_now: the global factor
+ * (early exaggeration) times the selective one of Sec. 4.3, which is tau at
+ * the iteration t_ref the point was refined and decays exponentially to 1
+ * with time constant `decay` iterations.  t_ref < 0 or t_ref > t_now: no
+ * selective exaggeration.
+ */
+static double exaggeration(const int32_t* t_ref, int64_t i, double tau, double decay, int32_t t_now,
+                           double global) {
+    double m = global;
+    if (t_ref && t_ref[i] >= 0 && t_ref[i] <= t_now)
+        m *= 1.0 + (tau - 1.0) * exp(-(double)(t_now - t_ref[i]) / decay);
+    return m;
+}
+
+/*
+ * F_i = m_i * sum_j p_ij q_ij Z (y_i - y_j), with q_ij Z = 1 / (1 + |y_i - y_j|^2)
+ * (Eq. 5, Eq. 6): the attractive term of the gradient of Eq. 7 (without the
+ * factor 4), over the sparse symmetric P given as CSR (row_ptr[N+1], col,
+ * val).  Y is N x dims (row-major), F is N x dims.  Returns 0, or -1 on bad
+ * arguments.
+ */
+int atsne_oracle_attractive(const int64_t* row_ptr, const int32_t* col, const double* val, int64_t N,
+                            const double* Y, int32_t dims, const int32_t* t_ref, double tau, double decay,
+                            int32_t t_now, double global, double* F) {
+    if (!row_ptr || !col || !val || !Y || !F || N < 1 || dims < 1 || dims > 8 || !(decay > 0.0)) return -1;
+    for (int64_t i = 0; i < N; ++i) {
+        double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+            const int32_t j = col[e];
+            if (j < 0 || j >= N) return -1;
+            double d2 = 0.0;
+            for (int32_t d = 0; d < dims; ++d) {
+                const double t = Y[i * dims + d] - Y[(int64_t)j * dims + d];
+                d2 += t * t;
+            }
+#if ORACLE_MUTANT == 10
+            const double w = val[e] / (1.0 + sqrt(d2)); /* planted: distance instead of squared distance */
+#else
+            const double w = val[e] / (1.0 + d2);
+#endif
+            for (int32_t d = 0; d < dims; ++d) {
+#if ORACLE_MUTANT == 11
+                acc[d] += w * (Y[(int64_t)j * dims + d] - Y[i * dims + d]); /* planted: wrong direction */
+#else
+                acc[d] += w * (Y[i * dims + d] - Y[(int64_t)j * dims + d]);
+#endif
+            }
+        }
+        const double m = exaggeration(t_ref, i, tau, decay, t_now, global);
+        for (int32_t d = 0; d < dims; ++d) F[i * dims + d] = m * acc[d];
+    }
+    return 0;
 }
 
 int atsne_oracle_mutant(void) { return ORACLE_MUTANT; }

@@ -10,6 +10,7 @@ Functions (each follows the passage cited in the C source):
   calibrate(d2, mu)                  bisection on beta to perplexity mu  -- Eq. 3, Eq. 4, Eq. 8
   symmetrize(idx_or_ptr, ...)        p_ij = (p_{j|i} + p_{i|j}) / 2N      -- Eq. 2, Eq. 10
   similarity(X, mu)                  the three steps chained, K = floor(3 mu)
+  attractive(row_ptr, col, val, Y)   F_attr of the gradient over sparse P  -- Eq. 5-7, Sec. 4.3
 
 Parity status: all functions pinned by ``tests/test_oracle_*.py``.
 """
@@ -59,6 +60,8 @@ class Oracle:
         L.atsne_oracle_calibrate.restype = ctypes.c_int
         L.atsne_oracle_symmetrize.argtypes = [p, p, p, i64, p, p, p, i64]
         L.atsne_oracle_symmetrize.restype = ctypes.c_int64
+        L.atsne_oracle_attractive.argtypes = [p, p, p, i64, p, i32, p, f64, f64, i32, f64, p]
+        L.atsne_oracle_attractive.restype = ctypes.c_int
         L.atsne_oracle_mutant.restype = ctypes.c_int
         L.atsne_oracle_max_threads.restype = ctypes.c_int
         self.mutant = L.atsne_oracle_mutant()
@@ -136,6 +139,23 @@ class Oracle:
         N, K = idx.shape
         ptr = np.arange(0, N * K + 1, K, dtype=np.int64)
         return self.symmetrize_csr(ptr, idx.reshape(-1), P.reshape(-1), N)
+
+    def attractive(self, row_ptr, col, val, Y, t_ref=None, tau: float = 1.0, decay: float = 1.0, t_now: int = 0,
+                   global_exag: float = 1.0):
+        """Attractive forces m_i sum_j p_ij (y_i - y_j) / (1 + |y_i - y_j|^2) (Eq. 5-7, Sec. 4.3)."""
+        row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        val = np.ascontiguousarray(val, dtype=np.float64)
+        Y = np.ascontiguousarray(Y, dtype=np.float64)
+        N, dims = Y.shape
+        tr = None if t_ref is None else np.ascontiguousarray(t_ref, dtype=np.int32)
+        F = np.empty((N, dims), np.float64)
+        rc = self.lib.atsne_oracle_attractive(self._ptr(row_ptr), self._ptr(col), self._ptr(val), N, self._ptr(Y),
+                                              dims, None if tr is None else self._ptr(tr), float(tau), float(decay),
+                                              int(t_now), float(global_exag), self._ptr(F))
+        if rc != 0:
+            raise ValueError("oracle attractive: bad arguments")
+        return F
 
     def similarity(self, X: np.ndarray, mu: float, K: int | None = None, nthreads: int = 0):
         """kNN -> calibration -> symmetrisation with K = floor(3 mu) (Sec. 3.1)."""

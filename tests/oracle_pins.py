@@ -302,8 +302,105 @@ def pin_pipeline_small(o):
     assert abs(r["val"].sum() - 1.0) < 1e-14
 
 
+# --------------------------------------------------------------------------
+# Attractive forces (Eq. 5-7) and selective exaggeration (Sec. 4.3)
+# --------------------------------------------------------------------------
+
+
+def _sym_csr(rng, N, deg):
+    """A random symmetric sparse pattern with positive values, as CSR."""
+    rows, cols = [], []
+    for i in range(N):
+        for j in rng.choice(N, size=deg, replace=False):
+            if j != i:
+                rows += [i, j]
+                cols += [j, i]
+    key = sorted(set(zip(rows, cols)))
+    vals = {}
+    for (i, j) in key:
+        if (j, i) in vals:
+            vals[(i, j)] = vals[(j, i)]
+        else:
+            vals[(i, j)] = float(rng.uniform(0.1, 1.0))
+    ptr = np.zeros(N + 1, np.int64)
+    for (i, _) in key:
+        ptr[i + 1] += 1
+    ptr = np.cumsum(ptr)
+    col = np.array([j for (_, j) in key], np.int32)
+    val = np.array([vals[k] for k in key], np.float64)
+    return ptr, col, val
+
+
+def pin_attr_two_points(o):
+    """Two points at distance 5: F_0 = p (y_0 - y_1) / (1 + 25), F_1 = -F_0."""
+    ptr = np.array([0, 1, 2], np.int64)
+    col = np.array([1, 0], np.int32)
+    val = np.array([0.5, 0.5])
+    Y = np.array([[0.0, 0.0], [3.0, 4.0]])
+    F = o.attractive(ptr, col, val, Y)
+    assert np.allclose(F, [[-1.5 / 26, -2.0 / 26], [1.5 / 26, 2.0 / 26]], rtol=1e-15, atol=0)
+
+
+def pin_attr_exact_rational(o):
+    """Four points with integer coordinates and rational p, summed exactly."""
+    Yq = [(0, 0), (1, 2), (-2, 1), (3, -1)]
+    P = {(0, 1): Fraction(1, 8), (0, 2): Fraction(1, 16), (1, 2): Fraction(3, 16), (1, 3): Fraction(1, 8),
+         (2, 3): Fraction(1, 32)}
+    P.update({(j, i): v for (i, j), v in list(P.items())})
+    key = sorted(P)
+    ptr = np.zeros(5, np.int64)
+    for (i, _) in key:
+        ptr[i + 1] += 1
+    ptr = np.cumsum(ptr)
+    F = o.attractive(ptr, np.array([j for _, j in key], np.int32), np.array([float(P[k]) for k in key]),
+                     np.array(Yq, np.float64))
+    for i in range(4):
+        for d in range(2):
+            exact = Fraction(0)
+            for (a, b), p in P.items():
+                if a != i:
+                    continue
+                d2 = sum((Yq[a][t] - Yq[b][t]) ** 2 for t in range(2))
+                exact += p * (Yq[a][d] - Yq[b][d]) / (1 + d2)
+            assert abs(F[i, d] - float(exact)) <= 1e-16 * max(1.0, abs(float(exact)))
+
+
+def pin_attr_invariants(o, seed: int = 13):
+    """Pairwise forces cancel (P symmetric), translation invariance, rotation
+    equivariance, linearity in P."""
+    rng = np.random.default_rng(seed)
+    ptr, col, val = _sym_csr(rng, 60, 5)
+    Y = rng.normal(size=(60, 2)) * 3
+    F = o.attractive(ptr, col, val, Y)
+    scale = np.abs(F).sum()
+    assert np.abs(F.sum(axis=0)).max() <= 1e-13 * scale
+    assert np.allclose(o.attractive(ptr, col, val, Y + np.array([5.0, -7.0])), F, rtol=1e-11, atol=1e-14)
+    th = 0.7
+    R = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]])
+    assert np.allclose(o.attractive(ptr, col, val, Y @ R), F @ R, rtol=1e-10, atol=1e-13)
+    assert np.allclose(o.attractive(ptr, col, 3.0 * val, Y), 3.0 * F, rtol=1e-14, atol=0)
+
+
+def pin_attr_exaggeration(o):
+    """Multiplier tau at the refine iteration, 1 + (tau - 1)/2 after decay ln 2
+    iterations, 1 when never refined or refined later; the global factor multiplies."""
+    ptr = np.array([0, 1, 2, 3, 4, 4], np.int64)
+    col = np.array([1, 0, 3, 2], np.int32)
+    val = np.full(4, 0.25)
+    Y = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 2.0], [0.0, 0.0], [9.0, 9.0]])
+    base = o.attractive(ptr, col, val, Y)
+    t_now = 100
+    decay = 20.0 / np.log(2.0)
+    t_ref = np.array([100, 80, -1, 150, 3], np.int32)
+    F = o.attractive(ptr, col, val, Y, t_ref=t_ref, tau=12.0, decay=decay, t_now=t_now, global_exag=2.0)
+    m = np.array([12.0, 1.0 + 11.0 / 2.0, 1.0, 1.0, 1.0]) * 2.0
+    assert np.allclose(F, base * m[:, None], rtol=1e-14, atol=0)
+    assert np.all(F[4] == 0.0)  # an isolated point feels no attraction
+
+
 KNN_PINS = [pin_knn_exact_rational, pin_knn_line, pin_knn_sklearn, pin_knn_metamorphic, pin_knn_subset]
 CAL_PINS = [pin_calibrate_two_level, pin_calibrate_progression, pin_calibrate_invariants,
             pin_calibrate_scaling, pin_calibrate_degenerate, pin_calibrate_brentq]
 SYM_PINS = [pin_symmetrize_hand, pin_symmetrize_dense, pin_pipeline_small]
-ALL_PINS = KNN_PINS + CAL_PINS + SYM_PINS
+ATTR_PINS = [pin_attr_two_points, pin_attr_exact_rational, pin_attr_invariants, pin_attr_exaggeration]
+ALL_PINS = KNN_PINS + CAL_PINS + SYM_PINS + ATTR_PINS

@@ -4,7 +4,8 @@ Each mutant is the oracle compiled with -DORACLE_MUTANT=n, which plants one
 plausible bug (tie rule reversed, self not excluded, a coordinate dropped, L1
 instead of squared L2, kernel width off by two, a term missing from the
 normaliser, the shift sign flipped, normaliser N instead of 2N, mirrored
-term dropped).  The test passes only if some pin fails on every mutant.
+term dropped, distance for squared distance in the attraction kernel, force
+direction reversed).  The test passes only if some pin fails on every mutant.
 """
 import pytest
 
@@ -15,6 +16,7 @@ MUTANTS = {
     1: pins.KNN_PINS, 2: pins.KNN_PINS, 3: pins.KNN_PINS, 4: pins.KNN_PINS,
     5: pins.CAL_PINS, 6: pins.CAL_PINS, 7: pins.CAL_PINS,
     8: pins.SYM_PINS, 9: pins.SYM_PINS,
+    10: pins.ATTR_PINS, 11: pins.ATTR_PINS,
 }
 
 
