@@ -23,6 +23,7 @@ import time
 import numpy as np
 
 PEAK = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}  # dense MFMA TFLOP/s, MI355X
+PEAK_HBM_GBS = 8000.0  # HBM3E, MI355X
 
 
 def parse():
@@ -105,7 +106,37 @@ def run_path(A, torch, Xt, mu, k, prec, steps, warmup):
         stages[name] = (ms, n)
     A.profile_enable(False)
     flags = fl.cpu().numpy()
-    return dict(wall=wall, stages=stages, idx=idx, P=P, val=val, flags=flags)
+    return dict(wall=wall, stages=stages, idx=idx, P=P, rp=rp, col=col, val=val, flags=flags)
+
+
+def attractive_leg(A, torch, rp, col, val, reps=50, warm=5, seed=7):
+    """Attractive forces (Eq. 7) over the step's symmetric P with a random 2-D
+    embedding and 10% of points under selective exaggeration.  HBM bytes per
+    launch: the CSR stream (8 B per entry + 8 B per row pointer), the
+    embedding read once and the forces written (8 B per point each), and the
+    refinement iterations (4 B per point)."""
+    N = rp.shape[0] - 1
+    nnz = int(col.shape[0])
+    rng = np.random.default_rng(seed)
+    Y = torch.from_numpy((rng.normal(size=(N, 2)) * 20.0).astype(np.float32)).cuda()
+    t_ref = torch.from_numpy(np.where(rng.random(N) < 0.1, rng.integers(0, 100, N), -1).astype(np.int32)).cuda()
+    F = torch.empty((N, 2), dtype=torch.float32, device="cuda")
+    for _ in range(warm):
+        A.attractive_forces(rp, col, val, Y, t_ref=t_ref, tau=12.0, decay=25.0, t_now=100, out=F)
+    torch.cuda.synchronize()
+    A.profile_enable(True)
+    for _ in range(reps):
+        A.attractive_forces(rp, col, val, Y, t_ref=t_ref, tau=12.0, decay=25.0, t_now=100, out=F)
+    torch.cuda.synchronize()
+    ms, n = A.profile_read("attractive_rows")
+    A.profile_enable(False)
+    avg_s = ms / max(n, 1) * 1e-3
+    nbytes = nnz * 8 + (N + 1) * 8 + N * 8 * 2 + N * 4
+    gbs = nbytes / avg_s / 1e9
+    return {"N": N, "nnz": nnz, "avg_launch_ms": round(avg_s * 1e3, 4), "points_per_s": round(N / avg_s, 1),
+            "roofline": {"bound": "hbm", "kernel": "attractive_rows", "achieved": round(gbs, 1),
+                         "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
+                         "traffic": None, "algorithmic_bytes": nbytes}}
 
 
 def serve_load(A, torch, X, rate, n_req, n_warm, seed=5):
@@ -323,6 +354,10 @@ def main():
         log("serve: Poisson stream at %.0f req/s ..." % a.serve_rate)
         line["serve"] = serve_load(A, torch, X, a.serve_rate, a.serve_requests + 10, 10)
         log("serve: p50 %.1f ms, p99 %.1f ms" % (line["serve"]["p50_ms"], line["serve"]["p99_ms"]))
+    log("attractive forces over the step's P ...")
+    line["attractive"] = attractive_leg(A, torch, r["rp"], r["col"], r["val"])
+    log("attractive: %.4f ms/launch, %.0f GB/s" % (line["attractive"]["avg_launch_ms"],
+                                                   line["attractive"]["roofline"]["achieved"]))
     if not a.no_serve:
         log("window: sliding-window stream ...")
         line["window"] = window_stream(A, torch)

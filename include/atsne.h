@@ -167,6 +167,30 @@ atsne_status atsne_symmetrize_csr(const int64_t* in_ptr, const int32_t* in_col, 
                                   int64_t N, int64_t nnz_in_host, int64_t* row_ptr, int32_t* col, float* val,
                                   int64_t* nnz_host, void* ws, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------- attractive forces -- */
+
+/* Attractive term of the gradient (Eq. 7) over the sparse symmetric P, the
+ * consumer of atsne_symmetrize's output:
+ *   F_i = m_i * sum_j p_ij (y_i - y_j) / (1 + |y_i - y_j|^2)
+ * with q_ij Z = 1/(1 + |y_i - y_j|^2) from Eq. 5 and Eq. 6; the factor 4 of
+ * Eq. 7 is left to the caller.  m_i = global_exaggeration, times
+ * 1 + (tau - 1) exp(-(t_now - t_ref[i]) / decay) when 0 <= t_ref[i] <= t_now:
+ * the selective exaggeration with exponential decay of Sec. 4.3 (a point
+ * refined at iteration t_ref[i] starts at tau).
+ *   row_ptr [N+1] int64, col [nnz] int32, val [nnz] FP32: device CSR of P
+ *           (as written by atsne_symmetrize); entries whose column is outside
+ *           [0, N) are skipped, row ends are clamped to nnz.
+ *   Y       [N x dims] FP32 device, row-major embedding; dims is 2 or 3.
+ *   t_ref   [N] int32 device iteration of each point's last refinement
+ *           (negative: never), or NULL for no selective exaggeration.
+ *   F       [N x dims] FP32 device out.
+ * Asynchronous on `stream`.  Errors: E_INVALID_ARG (null pointers, negative
+ * sizes, decay <= 0 with t_ref), E_UNSUPPORTED (dims). */
+atsne_status atsne_attractive_forces(const int64_t* row_ptr, const int32_t* col, const float* val, int64_t N,
+                                     int64_t nnz, const float* Y, int32_t dims, const int32_t* t_ref, float tau,
+                                     float decay, int32_t t_now, float global_exaggeration, float* F,
+                                     void* stream);
+
 /* --------------------------------------------------------------- serving -- */
 /* A server owns a device-resident corpus and its exact similarity state
  * (neighbour lists, conditional rows, beta) and processes requests with
@@ -181,9 +205,10 @@ atsne_status atsne_symmetrize_csr(const int64_t* in_ptr, const int32_t* in_col, 
  *           user selection of M resident points is recomputed at a requested
  *           perplexity (K_i = floor(3 mu_i) per row).
  *   delete  (Sec. 5.3): points leave the corpus; every resident list drops
- *           them without a replacement (the hole can be filled by later
- *           inserts), the row's precision rho_i falls by 1/K per removed
- *           neighbour, and changed rows are re-calibrated.  Inserting new
+ *           them without a replacement, the row's precision rho_i falls by
+ *           1/K per removed neighbour, and changed rows are re-calibrated.
+ *           A shortened list stays short: Eq. 13 compares with, and evicts,
+ *           the farthest neighbour still listed.  Inserting new
  *           points and deleting the oldest gives the sliding window of Sec. 8.
  * Inserts and deletes are commits, applied in arrival order.  Every request
  * carries a view (`epoch`): the number of commits submitted before it.  A

@@ -26,6 +26,7 @@ EXPORTS = [
     "atsne_knn_workspace_size", "atsne_knn", "atsne_knn_subset",
     "atsne_calibrate_p",
     "atsne_symmetrize_workspace_size", "atsne_symmetrize", "atsne_symmetrize_csr",
+    "atsne_attractive_forces",
     "atsne_serve_create", "atsne_serve_submit_insert", "atsne_serve_submit_refine", "atsne_serve_submit_delete",
     "atsne_serve_poll",
     "atsne_serve_wait", "atsne_serve_release", "atsne_serve_stats_get", "atsne_serve_snapshot",
@@ -89,6 +90,7 @@ def load(path: Path | None = None) -> ctypes.CDLL:
         "atsne_symmetrize_workspace_size": [_i64, _i64, _p],
         "atsne_symmetrize": [_p, _p, _i64, _i32, _p, _p, _p, _p, _p, _sz, _p],
         "atsne_symmetrize_csr": [_p, _p, _p, _i64, _i64, _p, _p, _p, _p, _p, _sz, _p],
+        "atsne_attractive_forces": [_p, _p, _p, _i64, _i64, _p, _i32, _p, _f32, _f32, _i32, _f32, _p, _p],
         "atsne_serve_create": [_p, _p, _i64, _i32, _f32, _p],
         "atsne_serve_submit_insert": [_p, _p, _i32, _p],
         "atsne_serve_submit_refine": [_p, _p, _i32, _f32, _p],
@@ -226,6 +228,28 @@ def similarity(X: torch.Tensor, perplexity: float, prec: str = "fp32", k: int | 
     P, beta, perp, flags = calibrate_p(d2, perplexity, flags=flags, stream=stream)
     row_ptr, col, val = symmetrize(idx, P, stream=stream)
     return dict(idx=idx, d2=d2, flags=flags, P=P, beta=beta, perp=perp, row_ptr=row_ptr, col=col, val=val)
+
+
+def attractive_forces(row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, Y: torch.Tensor,
+                      t_ref: torch.Tensor | None = None, tau: float = 1.0, decay: float = 1.0, t_now: int = 0,
+                      global_exaggeration: float = 1.0, stream=None, out: torch.Tensor | None = None):
+    """F_attr of Eq. 7 over the symmetric CSR P (Sec. 4.3 exaggeration); returns F [N, dims]."""
+    _dev(row_ptr, torch.int64, "row_ptr")
+    _dev(Y, torch.float32, "Y")
+    N, dims = Y.shape
+    nnz = int(col.shape[0])
+    if nnz:
+        _dev(col, torch.int32, "col")
+        _dev(val, torch.float32, "val")
+    if t_ref is not None:
+        _dev(t_ref, torch.int32, "t_ref")
+    Yc = Y.contiguous()
+    F = out if out is not None else torch.empty((N, dims), dtype=torch.float32, device=Y.device)
+    _check(load().atsne_attractive_forces(_ptr(row_ptr), _ptr(col) if nnz else None, _ptr(val) if nnz else None,
+                                          N, nnz, _ptr(Yc), dims, _ptr(t_ref), float(tau),
+                                          float(decay), int(t_now), float(global_exaggeration), _ptr(F),
+                                          _stream(stream)))
+    return F
 
 
 def device_info():

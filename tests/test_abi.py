@@ -47,6 +47,15 @@ def test_host_side_validation():
     assert L.atsne_symmetrize_workspace_size(100, 900, ctypes.byref(b)) == atsne.OK
     assert L.atsne_serve_create(None, None, 0, 0, 30.0, None) == atsne.E_INVALID_ARG
     assert b"bad arguments" in L.atsne_last_error()
+    # attractive forces: empty input is a no-op; checks precede any launch
+    assert L.atsne_attractive_forces(None, None, None, 0, 0, None, 2, None, 1.0, 1.0, 0, 1.0, None, None) == atsne.OK
+    assert L.atsne_attractive_forces(None, None, None, 5, 0, None, 2, None, 1.0, 1.0, 0, 1.0, None,
+                                     None) == atsne.E_INVALID_ARG
+    fake = ctypes.c_void_p(16)  # never dereferenced: the call fails before use
+    assert L.atsne_attractive_forces(fake, fake, fake, 5, 9, fake, 4, None, 1.0, 1.0, 0, 1.0, fake,
+                                     None) == atsne.E_UNSUPPORTED
+    assert L.atsne_attractive_forces(fake, fake, fake, 5, 9, fake, 2, fake, 4.0, 0.0, 0, 1.0, fake,
+                                     None) == atsne.E_INVALID_ARG
 
 
 @pytest.mark.parametrize("prec,k,kc", [(0, 90, 0), (1, 90, 0), (2, 150, 0), (0, 90, 90)])
