@@ -106,7 +106,7 @@ def run_path(A, torch, Xt, mu, k, prec, steps, warmup):
         stages[name] = (ms, n)
     A.profile_enable(False)
     flags = fl.cpu().numpy()
-    return dict(wall=wall, stages=stages, idx=idx, P=P, rp=rp, col=col, val=val, flags=flags)
+    return dict(wall=wall, stages=stages, idx=idx, d2=d2, P=P, beta=beta, rp=rp, col=col, val=val, flags=flags)
 
 
 def attractive_leg(A, torch, rp, col, val, reps=50, warm=5, seed=7):
@@ -137,6 +137,27 @@ def attractive_leg(A, torch, rp, col, val, reps=50, warm=5, seed=7):
             "roofline": {"bound": "hbm", "kernel": "attractive_rows", "achieved": round(gbs, 1),
                          "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
                          "traffic": None, "algorithmic_bytes": nbytes}}
+
+
+def order_leg(A, torch, idx, d2, beta, reps=5, seed=9):
+    """Refinement orderings (Sec. 5.1) on the step's kNN graph: density order of
+    all points, and the breadth-first visit (hops and path length) from 16
+    seeds.  Wall time per call, synchronisations included."""
+    rng = np.random.default_rng(seed)
+    seeds = torch.from_numpy(rng.choice(idx.shape[0], size=16, replace=False).astype(np.int32)).cuda()
+    out = {}
+    for name, fn in [("density_ms", lambda: A.order_density(beta)),
+                     ("bfs_hops_ms", lambda: A.order_neighbourhood(idx, None, seeds)),
+                     ("bfs_path_length_ms", lambda: A.order_neighbourhood(idx, d2, seeds, weighted=True))]:
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = fn()
+        torch.cuda.synchronize()
+        out[name] = round((time.perf_counter() - t0) / reps * 1e3, 3)
+    out["reached_from_16_seeds"] = int(r[0].shape[0])
+    return out
 
 
 def serve_load(A, torch, X, rate, n_req, n_warm, seed=5):
@@ -358,6 +379,9 @@ def main():
     line["attractive"] = attractive_leg(A, torch, r["rp"], r["col"], r["val"])
     log("attractive: %.4f ms/launch, %.0f GB/s" % (line["attractive"]["avg_launch_ms"],
                                                    line["attractive"]["roofline"]["achieved"]))
+    log("refinement orderings ...")
+    line["order"] = order_leg(A, torch, r["idx"], r["d2"], r["beta"])
+    log("order: %s" % line["order"])
     if not a.no_serve:
         log("window: sliding-window stream ...")
         line["window"] = window_stream(A, torch)

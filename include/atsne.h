@@ -191,6 +191,47 @@ atsne_status atsne_attractive_forces(const int64_t* row_ptr, const int32_t* col,
                                      float decay, int32_t t_now, float global_exaggeration, float* F,
                                      void* stream);
 
+/* -------------------------------------------------- refinement ordering -- */
+
+/* Orderings of Sec. 5.1 that decide which points to refine first (the
+ * caller then issues refine requests in that order).  Scratch: at most
+ * atsne_order_workspace_size(max(N, M)) bytes; ws may be NULL (then the
+ * library allocates stream-ordered scratch). */
+atsne_status atsne_order_workspace_size(int64_t N, size_t* bytes);
+
+/* Density-based refinement (Sec. 5.1): the selection `ids` (device int32
+ * [M], or NULL for all N points, M == N) sorted by sigma_i descending, i.e.
+ * beta_i ascending (sigma_i = 1/sqrt(2 beta_i), beta from
+ * atsne_calibrate_p), ties by index: points of sparse regions first.
+ *   beta       [N] FP32 device.
+ *   order_out  [M] int32 device out.
+ * Asynchronous, except that a selection is validated with one
+ * synchronisation (E_INVALID_ARG if an id is outside [0, N)). */
+atsne_status atsne_order_density(const float* beta, int64_t N, const int32_t* ids, int64_t M, int32_t* order_out,
+                                 void* ws, size_t ws_bytes, void* stream);
+
+/* Breadth-first refinement (Sec. 5.1): a visit of the graph of the kNN
+ * relationships (edge i -> j for every j in N_i; index -1 is no edge) from
+ * the user selection `seeds`.
+ *   weighted = 0: hop count from the nearest seed (the breadth-first visit);
+ *                 max_depth >= 0 stops the visit at that many hops.
+ *   weighted = 1: the visit driven by a priority queue on high-dimensional
+ *                 distance: shortest path length from the selection with
+ *                 edge weight ||x_i - x_j|| = sqrt(nbr_d2) (FP32 sums; the
+ *                 result is the least fixed point, independent of
+ *                 scheduling); max_depth must be negative.
+ *   nbr_idx [N x k] int32, nbr_d2 [N x k] FP32 device (as from atsne_knn).
+ *   seeds   [n_seeds] int32 device, in [0, N) (else E_INVALID_ARG).
+ *   key_out [N] FP32 device out (may be NULL): hop count or path length,
+ *           +inf for points the visit does not reach.
+ *   order_out [N] int32 device out: the reached points sorted by
+ *           (key, index); *n_reached_host (HOST) receives their number.
+ * Synchronises once per visited level. */
+atsne_status atsne_order_neighbourhood(const int32_t* nbr_idx, const float* nbr_d2, int64_t N, int32_t k,
+                                       const int32_t* seeds, int64_t n_seeds, int32_t weighted, int32_t max_depth,
+                                       float* key_out, int32_t* order_out, int64_t* n_reached_host, void* ws,
+                                       size_t ws_bytes, void* stream);
+
 /* --------------------------------------------------------------- serving -- */
 /* A server owns a device-resident corpus and its exact similarity state
  * (neighbour lists, conditional rows, beta) and processes requests with

@@ -26,7 +26,7 @@ EXPORTS = [
     "atsne_knn_workspace_size", "atsne_knn", "atsne_knn_subset",
     "atsne_calibrate_p",
     "atsne_symmetrize_workspace_size", "atsne_symmetrize", "atsne_symmetrize_csr",
-    "atsne_attractive_forces",
+    "atsne_attractive_forces", "atsne_order_workspace_size", "atsne_order_density", "atsne_order_neighbourhood",
     "atsne_serve_create", "atsne_serve_submit_insert", "atsne_serve_submit_refine", "atsne_serve_submit_delete",
     "atsne_serve_poll",
     "atsne_serve_wait", "atsne_serve_release", "atsne_serve_stats_get", "atsne_serve_snapshot",
@@ -91,6 +91,10 @@ def load(path: Path | None = None) -> ctypes.CDLL:
         "atsne_symmetrize": [_p, _p, _i64, _i32, _p, _p, _p, _p, _p, _sz, _p],
         "atsne_symmetrize_csr": [_p, _p, _p, _i64, _i64, _p, _p, _p, _p, _p, _sz, _p],
         "atsne_attractive_forces": [_p, _p, _p, _i64, _i64, _p, _i32, _p, _f32, _f32, _i32, _f32, _p, _p],
+        "atsne_order_workspace_size": [_i64, _p],
+        "atsne_order_density": [_p, _i64, _p, _i64, _p, _p, ctypes.c_size_t, _p],
+        "atsne_order_neighbourhood": [_p, _p, _i64, _i32, _p, _i64, _i32, _i32, _p, _p, _p, _p, ctypes.c_size_t,
+                                      _p],
         "atsne_serve_create": [_p, _p, _i64, _i32, _f32, _p],
         "atsne_serve_submit_insert": [_p, _p, _i32, _p],
         "atsne_serve_submit_refine": [_p, _p, _i32, _f32, _p],
@@ -250,6 +254,35 @@ def attractive_forces(row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tenso
                                           float(decay), int(t_now), float(global_exaggeration), _ptr(F),
                                           _stream(stream)))
     return F
+
+
+def order_density(beta: torch.Tensor, ids: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Density-based refinement order (Sec. 5.1): ids by sigma descending, ties by index."""
+    _dev(beta, torch.float32, "beta")
+    N = beta.shape[0]
+    if ids is not None:
+        _dev(ids, torch.int32, "ids")
+    M = N if ids is None else ids.shape[0]
+    out = torch.empty((M,), dtype=torch.int32, device=beta.device)
+    _check(load().atsne_order_density(_ptr(beta), N, _ptr(ids), M, _ptr(out), None, 0, _stream(stream)))
+    return out
+
+
+def order_neighbourhood(nbr_idx: torch.Tensor, nbr_d2: torch.Tensor | None, seeds: torch.Tensor,
+                        weighted: bool = False, max_depth: int = -1, stream=None):
+    """Breadth-first refinement order (Sec. 5.1).  Returns (order [n_reached], key [N])."""
+    _dev(nbr_idx, torch.int32, "nbr_idx")
+    _dev(seeds, torch.int32, "seeds")
+    if weighted:
+        _dev(nbr_d2, torch.float32, "nbr_d2")
+    N, k = nbr_idx.shape
+    key = torch.empty((N,), dtype=torch.float32, device=nbr_idx.device)
+    order = torch.empty((N,), dtype=torch.int32, device=nbr_idx.device)
+    n = ctypes.c_int64()
+    _check(load().atsne_order_neighbourhood(_ptr(nbr_idx.contiguous()), _ptr(nbr_d2) if weighted else None, N, k,
+                                            _ptr(seeds), seeds.shape[0], 1 if weighted else 0, int(max_depth),
+                                            _ptr(key), _ptr(order), ctypes.byref(n), None, 0, _stream(stream)))
+    return order[: n.value], key
 
 
 def device_info():
