@@ -15,6 +15,9 @@
  *     difference.  Self is excluded by index (the k != i of Eq. 3).  Ties are
  *     broken by the lower index, i.e. rows are ordered by the key (d, j).
  *     K = floor(3*mu) is the neighbourhood size of Sec. 3.1 (Eq. 8).
+ *   - atsne_oracle_knn_candidates: the same ranking restricted to a
+ *     per-query candidate set (the definition of a candidate-restricted,
+ *     approximate search).
  *   - atsne_oracle_calibrate: per row, the Gaussian precision beta = 1/(2
  *     sigma^2) of Eq. 3 restricted to the neighbour set (Eq. 8) such that the
  *     row's perplexity (Eq. 4) equals mu, found by bisection on beta.  The
@@ -192,6 +195,74 @@ int atsne_oracle_knn(const float* X, int64_t N, int32_t D, int64_t ld,
             for (int32_t t = 0; t < K; ++t) {
                 idx[m * K + t] = heap[t].j;
                 d2[m * K + t] = heap[t].d;
+            }
+            if (d2_next) d2_next[m] = (n > K) ? heap[K].d : INFINITY;
+        }
+        free(heap);
+    }
+    return bad ? -1 : 0;
+}
+
+/*
+ * Exact kNN of each query over its own candidate set: query m (corpus row
+ * query_ids[m]) ranks the rows cand_idx[cand_ptr[m] .. cand_ptr[m+1]) other
+ * than itself by (d, j) and keeps the first K; when fewer than K remain, the
+ * tail is index -1 with distance +inf.  d2_next as for atsne_oracle_knn.
+ * This is the definition of a candidate-restricted (approximate) search.
+ * Returns 0, or -1 on bad arguments.
+ */
+int atsne_oracle_knn_candidates(const float* X, int64_t N, int32_t D, int64_t ld, const int32_t* query_ids,
+                                int64_t M, const int64_t* cand_ptr, const int32_t* cand_idx, int32_t K,
+                                int32_t* idx, double* d2, double* d2_next, int32_t nthreads) {
+    if (!X || !query_ids || !cand_ptr || !idx || !d2 || N < 1 || D < 1 || ld < D || K < 1 || M < 0) return -1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    int bad = 0;
+#pragma omp parallel
+    {
+        entry_t* heap = (entry_t*)malloc(sizeof(entry_t) * (size_t)(K + 1));
+        if (!heap) {
+#pragma omp atomic write
+            bad = 1;
+        }
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t m = 0; m < M; ++m) {
+            if (!heap) continue;
+            const int64_t q = query_ids[m];
+            if (q < 0 || q >= N) {
+#pragma omp atomic write
+                bad = 1;
+                continue;
+            }
+            const float* xq = X + q * ld;
+            int n = 0;
+            for (int64_t e0 = cand_ptr[m]; e0 < cand_ptr[m + 1]; ++e0) {
+                const int64_t j = cand_idx[e0];
+                if (j < 0 || j >= N) {
+#pragma omp atomic write
+                    bad = 1;
+                    continue;
+                }
+                if (j == q) continue;
+                entry_t e;
+                e.d = sq_dist(xq, X + j * ld, D);
+                e.j = (int32_t)j;
+                if (n < K + 1) {
+                    heap[n] = e;
+                    heap_sift_up(heap, n);
+                    ++n;
+                } else if (key_less(e, heap[0])) {
+                    heap[0] = e;
+                    heap_sift_down(heap, n, 0);
+                }
+            }
+            qsort(heap, (size_t)n, sizeof(entry_t), cmp_entry);
+            for (int32_t t = 0; t < K; ++t) {
+                idx[m * K + t] = t < n ? heap[t].j : -1;
+                d2[m * K + t] = t < n ? heap[t].d : INFINITY;
             }
             if (d2_next) d2_next[m] = (n > K) ? heap[K].d : INFINITY;
         }

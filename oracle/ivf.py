@@ -1,0 +1,132 @@
+"""Cluster-pruned search: the precision-controlled approximate kNN --
+TEST INFRASTRUCTURE ONLY.
+
+Only the test suite may import this module; the GPU library never does, and
+the two share no code.  The paper reaches a requested precision rho (Eq. 9)
+with a randomized kd-forest whose parameters are fitted to rho (Sec. 4.2).
+The GPU path reaches it with a cluster-pruned brute-force search instead,
+and this module holds that search's definition, step by step, in FP64:
+
+  lloyd_update(X, assign, prev)  k-means update: each centroid is the mean of
+                                 its members; an empty cluster keeps its centroid.
+  nearest_centroid(X, cent)      k-means assignment: the nearest centroid by
+                                 (squared distance, index).
+  cluster_order(assign, C)       the corpus sorted by (cluster, index): the
+                                 permutation and each cluster's row range.
+  probe_order(cent)              per cluster, all clusters by (distance
+                                 between centroids, index), itself first.
+  candidate_tiles(start, probe, n_probe, K, N)
+                                 per cluster, the 256-row tiles of the sorted
+                                 corpus that overlap its first n_probe probe
+                                 clusters, extended with further probe
+                                 clusters until the tiles hold at least K + 1
+                                 rows.  A point's candidates are the rows of
+                                 its own cluster's tiles.
+  search(X, K, assign, C, cent, n_probe)
+                                 exact kNN of every point over its candidates.
+  precision(approx, exact)       Eq. 9: mean over rows of |N^A_i & N_i| / K.
+
+Parity status: pinned by ``tests/test_oracle_ivf.py`` (reduction to plain
+kNN, brute force on small inputs, scipy distances, hand examples, the k-means
+objective never increasing).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from oracle import oracle as O
+
+TILE = 256
+
+
+def sqdist(A, B):
+    A = np.asarray(A, np.float64)
+    B = np.asarray(B, np.float64)
+    out = np.empty((A.shape[0], B.shape[0]))
+    step = max(1, (1 << 22) // max(1, B.shape[0] * A.shape[1]))
+    for s in range(0, A.shape[0], step):
+        diff = A[s:s + step, None, :] - B[None, :, :]
+        out[s:s + step] = np.einsum("rbd,rbd->rb", diff, diff)
+    return out
+
+
+def lloyd_update(X, assign, prev):
+    X = np.asarray(X, np.float64)
+    cent = np.array(prev, np.float64, copy=True)
+    for c in range(cent.shape[0]):
+        mem = np.flatnonzero(assign == c)
+        if mem.size:
+            cent[c] = X[mem].mean(axis=0)
+    return cent
+
+
+def nearest_centroid(X, cent):
+    D = sqdist(X, cent)
+    # ties by the lower centroid index: argmin returns the first minimum
+    return np.argmin(D, axis=1).astype(np.int32)
+
+
+def cluster_order(assign, C):
+    assign = np.asarray(assign, np.int64)
+    perm = np.lexsort((np.arange(assign.size), assign)).astype(np.int32)
+    counts = np.bincount(assign, minlength=C)
+    start = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    return perm, start
+
+
+def probe_order(cent):
+    D = sqdist(cent, cent)
+    C = D.shape[0]
+    out = np.empty((C, C), np.int32)
+    for c in range(C):
+        key = D[c].copy()
+        key[c] = -1.0  # itself first
+        out[c] = np.lexsort((np.arange(C), key))
+    return out
+
+
+def candidate_tiles(start, probe, n_probe, K, N):
+    C = probe.shape[0]
+    tiles = []
+    for c in range(C):
+        cover = set()
+        used = 0
+        for p in probe[c]:
+            if used >= n_probe and len(cover) > 0 and _rows(cover, N) >= K + 1:
+                break
+            used += 1
+            lo, hi = int(start[p]), int(start[p + 1])
+            if hi > lo:
+                cover.update(range(lo // TILE, (hi - 1) // TILE + 1))
+        tiles.append(sorted(cover))
+    return tiles
+
+
+def _rows(cover, N):
+    return sum(min(N, (t + 1) * TILE) - t * TILE for t in cover)
+
+
+def search(X, K, assign, C, cent, n_probe, oracle=None):
+    """Approximate kNN of every point (original ids); also returns each row's candidate count."""
+    ora = oracle or O.get()
+    N = X.shape[0]
+    perm, start = cluster_order(assign, C)
+    tiles = candidate_tiles(start, probe_order(cent), n_probe, K, N)
+    ptr = [0]
+    cand = []
+    for i in range(N):
+        rows = []
+        for t in tiles[assign[i]]:
+            rows.extend(perm[t * TILE:min(N, (t + 1) * TILE)].tolist())
+        cand.extend(rows)
+        ptr.append(len(cand))
+    idx, d2, nxt = ora.knn_candidates(X, K, np.arange(N, dtype=np.int32), np.array(ptr), np.array(cand, np.int32))
+    return idx, d2, nxt, np.diff(np.array(ptr))
+
+
+def precision(approx, exact):
+    M, K = exact.shape
+    tot = 0
+    for a, b in zip(approx, exact):
+        tot += len(np.intersect1d(a[a >= 0], b))
+    return tot / float(M * K)

@@ -7,6 +7,7 @@ code.
 
 Functions (each follows the passage cited in the C source):
   knn(X, K, query_ids=None)          exact brute-force kNN, key (d, j)   -- Eq. 3, Eq. 8
+  knn_candidates(X, K, q, ptr, idx)  the same over per-query candidate rows (approximate search)
   calibrate(d2, mu)                  bisection on beta to perplexity mu  -- Eq. 3, Eq. 4, Eq. 8
   symmetrize(idx_or_ptr, ...)        p_ij = (p_{j|i} + p_{i|j}) / 2N      -- Eq. 2, Eq. 10
   similarity(X, mu)                  the three steps chained, K = floor(3 mu)
@@ -60,6 +61,8 @@ class Oracle:
         L.atsne_oracle_calibrate.restype = ctypes.c_int
         L.atsne_oracle_symmetrize.argtypes = [p, p, p, i64, p, p, p, i64]
         L.atsne_oracle_symmetrize.restype = ctypes.c_int64
+        L.atsne_oracle_knn_candidates.argtypes = [p, i64, i32, i64, p, i64, p, p, i32, p, p, p, i32]
+        L.atsne_oracle_knn_candidates.restype = ctypes.c_int
         L.atsne_oracle_attractive.argtypes = [p, p, p, i64, p, i32, p, f64, f64, i32, f64, p]
         L.atsne_oracle_attractive.restype = ctypes.c_int
         L.atsne_oracle_mutant.restype = ctypes.c_int
@@ -94,6 +97,27 @@ class Oracle:
                                        self._ptr(idx), self._ptr(d2), self._ptr(nxt), int(nthreads))
         if rc != 0:
             raise ValueError("oracle knn: bad arguments")
+        return idx, d2, nxt
+
+    def knn_candidates(self, X: np.ndarray, K: int, query_ids, cand_ptr, cand_idx, nthreads: int = 0):
+        """Exact kNN of each query over its own candidate rows (absent tail: -1, +inf).
+
+        Returns (idx int32[M,K], d2 float64[M,K], d2_next float64[M]).
+        """
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        N, D = X.shape
+        qids = np.ascontiguousarray(query_ids, dtype=np.int32)
+        M = qids.shape[0]
+        cp = np.ascontiguousarray(cand_ptr, dtype=np.int64)
+        ci = np.ascontiguousarray(cand_idx, dtype=np.int32)
+        idx = np.empty((M, K), np.int32)
+        d2 = np.empty((M, K), np.float64)
+        nxt = np.empty((M,), np.float64)
+        rc = self.lib.atsne_oracle_knn_candidates(self._ptr(X), N, D, D, self._ptr(qids), M, self._ptr(cp),
+                                                  self._ptr(ci), K, self._ptr(idx), self._ptr(d2), self._ptr(nxt),
+                                                  int(nthreads))
+        if rc != 0:
+            raise ValueError("oracle knn_candidates: bad arguments")
         return idx, d2, nxt
 
     def calibrate(self, d2: np.ndarray, mu, max_iter: int = 2000, nthreads: int = 0):
