@@ -191,6 +191,48 @@ atsne_status atsne_attractive_forces(const int64_t* row_ptr, const int32_t* col,
                                      float decay, int32_t t_now, float global_exaggeration, float* F,
                                      void* stream);
 
+/* ------------------------------------ precision-controlled approximate kNN -- */
+
+/* The paper reaches a user precision rho (Eq. 9) with a randomized kd-forest
+ * whose parameters are fitted to rho (Sec. 4.2).  This library reaches it
+ * with a cluster-pruned brute-force search on the matrix cores:
+ *   build  k-means (Lloyd, `iters` updates) from the caller's initial points
+ *          init_ids_host[n_clusters] (distinct, in [0, N)); each update sets a
+ *          centroid to the mean of its members (an empty cluster keeps its
+ *          centroid); the assignment is the exact nearest centroid by
+ *          (squared distance, index), taken again after the last update.  The
+ *          corpus is sorted by (cluster, index); each cluster's probe order is
+ *          itself, then the other clusters by (centroid distance, index).
+ *   knn    every point's candidates are the rows of the 256-row tiles of the
+ *          sorted corpus that overlap its cluster's first n_probe probe
+ *          clusters (further probe clusters are added until the tiles hold at
+ *          least k + 1 rows); the result is the exact FP32 kNN over those
+ *          candidates (same re-rank, tie rule and FP64 near-tie handling as
+ *          atsne_knn).  n_probe >= n_clusters gives the exact kNN.
+ *   fit    the smallest n_probe whose precision (Eq. 9, against the exact
+ *          kNN) over all points of the sample clusters reaches rho; precision
+ *          never decreases with n_probe, so it is found by bisection.
+ * X is a device FP32 [N x D] corpus (copied; the index owns its memory).
+ * Limits: 2 <= n_clusters <= min(N, 1024), D <= 4096, k + max(32, k/2) <= 1024.
+ * All calls synchronise `stream`. */
+typedef struct atsne_ivf atsne_ivf;
+atsne_status atsne_ivf_build(const float* X, int64_t N, int32_t D, int32_t n_clusters, const int32_t* init_ids_host,
+                             int32_t iters, atsne_ivf** out, void* stream);
+/* The partition: assign [N] int32 device, centroids [n_clusters x D] FP32
+ * device, cluster_start_host [n_clusters + 1] (rows of the sorted corpus),
+ * probe_host [n_clusters x n_clusters]; any pointer may be NULL. */
+atsne_status atsne_ivf_partition(const atsne_ivf* ix, int32_t* assign, float* centroids, int64_t* cluster_start_host,
+                                 int32_t* probe_host, void* stream);
+/* Approximate kNN of all N points, in the layout of atsne_knn (neighbour ids
+ * are corpus ids; a row with fewer than k candidates would end in -1/+inf,
+ * which the k + 1 rule prevents).  *candidate_fraction_host (may be NULL):
+ * mean candidate rows per point / N, the work relative to the exact search. */
+atsne_status atsne_ivf_knn(atsne_ivf* ix, int32_t k, int32_t n_probe, int32_t* nbr_idx, float* nbr_d2,
+                           uint8_t* flags, double* candidate_fraction_host, void* stream);
+atsne_status atsne_ivf_fit(atsne_ivf* ix, int32_t k, float rho, const int32_t* sample_clusters_host, int32_t n_sample,
+                           int32_t* n_probe_out, float* rho_sample_out, void* stream);
+atsne_status atsne_ivf_destroy(atsne_ivf* ix);
+
 /* -------------------------------------------------- refinement ordering -- */
 
 /* Orderings of Sec. 5.1 that decide which points to refine first (the

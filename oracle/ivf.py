@@ -106,21 +106,23 @@ def _rows(cover, N):
     return sum(min(N, (t + 1) * TILE) - t * TILE for t in cover)
 
 
-def search(X, K, assign, C, cent, n_probe, oracle=None):
-    """Approximate kNN of every point (original ids); also returns each row's candidate count."""
+def search(X, K, assign, C, cent, n_probe, oracle=None, probe=None, rows=None):
+    """Approximate kNN of the points `rows` (default: all; original ids); also
+    returns each row's candidate count.  `probe` overrides the probe order
+    computed from `cent` (the partition is an input of the search)."""
     ora = oracle or O.get()
     N = X.shape[0]
+    assign = np.asarray(assign)
     perm, start = cluster_order(assign, C)
-    tiles = candidate_tiles(start, probe_order(cent), n_probe, K, N)
+    tiles = candidate_tiles(start, probe_order(cent) if probe is None else np.asarray(probe), n_probe, K, N)
+    rows = np.arange(N, dtype=np.int32) if rows is None else np.asarray(rows, np.int32)
     ptr = [0]
     cand = []
-    for i in range(N):
-        rows = []
+    for i in rows:
         for t in tiles[assign[i]]:
-            rows.extend(perm[t * TILE:min(N, (t + 1) * TILE)].tolist())
-        cand.extend(rows)
+            cand.extend(perm[t * TILE:min(N, (t + 1) * TILE)].tolist())
         ptr.append(len(cand))
-    idx, d2, nxt = ora.knn_candidates(X, K, np.arange(N, dtype=np.int32), np.array(ptr), np.array(cand, np.int32))
+    idx, d2, nxt = ora.knn_candidates(X, K, rows, np.array(ptr), np.array(cand, np.int32))
     return idx, d2, nxt, np.diff(np.array(ptr))
 
 

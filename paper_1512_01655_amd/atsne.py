@@ -26,6 +26,7 @@ EXPORTS = [
     "atsne_knn_workspace_size", "atsne_knn", "atsne_knn_subset",
     "atsne_calibrate_p",
     "atsne_symmetrize_workspace_size", "atsne_symmetrize", "atsne_symmetrize_csr",
+    "atsne_ivf_build", "atsne_ivf_partition", "atsne_ivf_knn", "atsne_ivf_fit", "atsne_ivf_destroy",
     "atsne_attractive_forces", "atsne_order_workspace_size", "atsne_order_density", "atsne_order_neighbourhood",
     "atsne_serve_create", "atsne_serve_submit_insert", "atsne_serve_submit_refine", "atsne_serve_submit_delete",
     "atsne_serve_poll",
@@ -91,6 +92,11 @@ def load(path: Path | None = None) -> ctypes.CDLL:
         "atsne_symmetrize": [_p, _p, _i64, _i32, _p, _p, _p, _p, _p, _sz, _p],
         "atsne_symmetrize_csr": [_p, _p, _p, _i64, _i64, _p, _p, _p, _p, _p, _sz, _p],
         "atsne_attractive_forces": [_p, _p, _p, _i64, _i64, _p, _i32, _p, _f32, _f32, _i32, _f32, _p, _p],
+        "atsne_ivf_build": [_p, _i64, _i32, _i32, _p, _i32, _p, _p],
+        "atsne_ivf_partition": [_p, _p, _p, _p, _p, _p],
+        "atsne_ivf_knn": [_p, _i32, _i32, _p, _p, _p, _p, _p],
+        "atsne_ivf_fit": [_p, _i32, _f32, _p, _i32, _p, _p, _p],
+        "atsne_ivf_destroy": [_p],
         "atsne_order_workspace_size": [_i64, _p],
         "atsne_order_density": [_p, _i64, _p, _i64, _p, _p, ctypes.c_size_t, _p],
         "atsne_order_neighbourhood": [_p, _p, _i64, _i32, _p, _i64, _i32, _i32, _p, _p, _p, _p, ctypes.c_size_t,
@@ -283,6 +289,67 @@ def order_neighbourhood(nbr_idx: torch.Tensor, nbr_d2: torch.Tensor | None, seed
                                             _ptr(seeds), seeds.shape[0], 1 if weighted else 0, int(max_depth),
                                             _ptr(key), _ptr(order), ctypes.byref(n), None, 0, _stream(stream)))
     return order[: n.value], key
+
+
+class IVF:
+    """Precision-controlled approximate kNN (atsne_ivf_*): cluster-pruned search."""
+
+    def __init__(self, X: torch.Tensor, n_clusters: int, iters: int = 10, seed: int = 0, init_ids=None, stream=None):
+        import numpy as np
+
+        _dev(X, torch.float32, "X")
+        X = X.contiguous()
+        self.N, self.D = X.shape
+        self.C = int(n_clusters)
+        if init_ids is None:
+            init_ids = np.random.default_rng(seed).choice(self.N, size=self.C, replace=False)
+        ids = np.ascontiguousarray(init_ids, dtype=np.int32)
+        self.h = ctypes.c_void_p()
+        _check(load().atsne_ivf_build(_ptr(X), self.N, self.D, self.C, ids.ctypes.data_as(_p), int(iters),
+                                      ctypes.byref(self.h), _stream(stream)))
+
+    def partition(self, stream=None):
+        """(assign [N] int32, centroids [C, D] FP32 device; cluster_start [C+1], probe [C, C] numpy)."""
+        import numpy as np
+
+        assign = torch.empty((self.N,), dtype=torch.int32, device="cuda")
+        cent = torch.empty((self.C, self.D), dtype=torch.float32, device="cuda")
+        start = np.empty((self.C + 1,), np.int64)
+        probe = np.empty((self.C, self.C), np.int32)
+        _check(load().atsne_ivf_partition(self.h, _ptr(assign), _ptr(cent), start.ctypes.data_as(_p),
+                                          probe.ctypes.data_as(_p), _stream(stream)))
+        return assign, cent, start, probe
+
+    def knn(self, k: int, n_probe: int, stream=None):
+        """(idx [N, k] int32, d2 [N, k] FP32, flags [N] uint8, candidate fraction)."""
+        idx = torch.empty((self.N, k), dtype=torch.int32, device="cuda")
+        d2 = torch.empty((self.N, k), dtype=torch.float32, device="cuda")
+        fl = torch.zeros((self.N,), dtype=torch.uint8, device="cuda")
+        frac = ctypes.c_double()
+        _check(load().atsne_ivf_knn(self.h, int(k), int(n_probe), _ptr(idx), _ptr(d2), _ptr(fl), ctypes.byref(frac),
+                                    _stream(stream)))
+        return idx, d2, fl, frac.value
+
+    def fit(self, k: int, rho: float, sample_clusters, stream=None):
+        """Smallest n_probe reaching precision rho on the sample clusters: (n_probe, sample precision)."""
+        import numpy as np
+
+        sc = np.ascontiguousarray(sample_clusters, dtype=np.int32)
+        n, r = ctypes.c_int32(), ctypes.c_float()
+        _check(load().atsne_ivf_fit(self.h, int(k), float(rho), sc.ctypes.data_as(_p), sc.size, ctypes.byref(n),
+                                    ctypes.byref(r), _stream(stream)))
+        return n.value, r.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            _check(load().atsne_ivf_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def device_info():

@@ -345,9 +345,20 @@ struct TileArgs {
     const int32_t* views;
     int32_t view;
     int MB, S, tiles_per_split, tile_lo, tile_hi, cap;
+    // tile lists (restricted search): block b holds rows [blk_q[b], blk_q[b+1])
+    // and searches the key tiles tl_idx[blk_t[b] .. blk_t[b+1])
+    const int32_t* blk_q;
+    const int32_t* blk_t;
+    const int32_t* tl_idx;
     uint64_t* slots;
     int32_t* counts;
 };
+
+// Instantiations of the tile kernel: the plain search, the search over a
+// corpus with deletion stamps (serving), and the search restricted to
+// per-block tile lists.  Separate instantiations keep the extra logic out of
+// the plain search's registers.
+enum TileMode { TILE_PLAIN = 0, TILE_VIS = 1, TILE_LIST = 2 };
 
 // Deletion visibility: key j exists for a request with view v iff it was not
 // deleted by one of the first v commits.
@@ -355,9 +366,7 @@ __device__ __forceinline__ bool key_visible(const int32_t* death, int64_t j, int
     return !death || death[j] >= view;
 }
 
-// VIS: the corpus carries deletion stamps (serving); a separate instantiation
-// so that the plain search keeps the visibility code out of its registers.
-template <int P, bool VIS>
+template <int P, int MODE>
 __global__ __launch_bounds__(TileGeom<P>::THREADS) __attribute__((amdgpu_waves_per_eu(TileGeom<P>::WPE, TileGeom<P>::WPE))) void knn_tile(TileArgs a) {
     constexpr int QB = TileGeom<P>::QB;
     constexpr int TILE_WAVES = TileGeom<P>::WAVES;
@@ -376,26 +385,49 @@ __global__ __launch_bounds__(TileGeom<P>::THREADS) __attribute__((amdgpu_waves_p
     const int t = threadIdx.x;
     const int l = t & 63;
     const int w = t >> 6;
+    constexpr bool VIS = MODE == TILE_VIS;
+    constexpr bool LIST = MODE == TILE_LIST;
     const int qb = blockIdx.x % a.MB;
     const int split = blockIdx.x / a.MB;
-    const int tile_begin = a.tile_lo + split * a.tiles_per_split;
-    const int tile_end = min(a.tile_hi, tile_begin + a.tiles_per_split);
+    // this block's query rows and this split's positions in its tile sequence
+    int64_t qbase, qend;
+    int tile_begin, tile_end;
+    if constexpr (LIST) {
+        qbase = a.blk_q[qb];
+        qend = a.blk_q[qb + 1];
+        const int l0 = a.blk_t[qb], l1 = a.blk_t[qb + 1];
+        const int tps = (l1 - l0 + a.S - 1) / a.S;
+        tile_begin = min(l1, l0 + split * tps);
+        tile_end = min(l1, tile_begin + tps);
+    } else {
+        qbase = (int64_t)qb * QB;
+        qend = a.M;
+        tile_begin = a.tile_lo + split * a.tiles_per_split;
+        tile_end = min(a.tile_hi, tile_begin + a.tiles_per_split);
+    }
+    // corpus tile at sequence position p
+    auto tile_id = [&](int p) __attribute__((always_inline)) {
+        if constexpr (LIST)
+            return a.tl_idx[p];
+        else
+            return p;
+    };
     uint32_t* hist = hist_all[w];
     const int64_t row_units = a.row_units;
     const int n_chunks = a.n_chunks;
 
     // Rows of the query tile this thread loads (4 rows, unit t & 7).
     auto qrow_of = [&](int i) {
-        const int64_t m = (int64_t)qb * QB + (t >> 3) + RSTEP * i;
-        const int64_t row = m < a.M ? load_qid(a.qids, a.m0, m) : 0;
+        const int64_t m = qbase + (t >> 3) + RSTEP * i;
+        const int64_t row = m < qend ? load_qid(a.qids, a.m0, m) : 0;
         return row * row_units + (t & 7);
     };
     const int64_t qoff0 = qrow_of(0), qoff1 = qrow_of(1), qoff2 = qrow_of(2), qoff3 = qrow_of(3);
 
     // Per-lane query state (lanes l and l+32 share query 32w + l%32).
     const int qloc = 32 * w + (l & 31);
-    const int64_t mq = (int64_t)qb * QB + qloc;
-    const bool qvalid = mq < a.M;
+    const int64_t mq = qbase + qloc;
+    const bool qvalid = mq < qend;
     const int64_t self = qvalid ? load_qid(a.qids, a.m0, mq) : -1;
     const int64_t nl = qvalid ? (a.nlims ? (int64_t)a.nlims[mq] : a.nlim) : 0;
     const int kcq = qvalid ? (a.kcs ? a.kcs[mq] : a.kc) : 0;
@@ -449,7 +481,7 @@ __global__ __launch_bounds__(TileGeom<P>::THREADS) __attribute__((amdgpu_waves_p
         pq2 = a.Xp[qoff2 + co_];                                                                     \
         pq3 = a.Xp[qoff3 + co_];                                                                     \
     } while (0)
-#define ATSNE_STORE_CHUNK(BUF, TILE, C)                                                              \
+#define ATSNE_STORE_CHUNK(BUF, POS, TILE, C)                                                         \
     do {                                                                                             \
         uint4* ks_ = &Ks[BUF][(t >> 3) * ROW_UNITS + (t & 7)];                                      \
         ks_[0] = pk0;                                                                                \
@@ -468,8 +500,8 @@ __global__ __launch_bounds__(TileGeom<P>::THREADS) __attribute__((amdgpu_waves_p
         qs_[2 * RSTEP * ROW_UNITS] = pq2;                                                            \
         qs_[3 * RSTEP * ROW_UNITS] = pq3;                                                            \
         if ((C) == 0 && t < KT) {                                                                    \
-            Kn[(TILE) % 3][t] = a.norms[(int64_t)(TILE) * KT + t];                                  \
-            if (P == ATSNE_PREC_FP8_E4M3) Ksc[(TILE) % 3][t] = a.scales[(int64_t)(TILE) * KT + t];  \
+            Kn[(POS) % 3][t] = a.norms[(int64_t)(TILE) * KT + t];                                   \
+            if (P == ATSNE_PREC_FP8_E4M3) Ksc[(POS) % 3][t] = a.scales[(int64_t)(TILE) * KT + t];   \
         }                                                                                            \
     } while (0)
 
@@ -506,7 +538,7 @@ __global__ __launch_bounds__(TileGeom<P>::THREADS) __attribute__((amdgpu_waves_p
         }
     };
 
-    auto epilogue = [&](int tile) __attribute__((always_inline)) {
+    auto epilogue = [&](int pos) __attribute__((always_inline)) {
         // make room, then filter this tile's candidates
         {
             uint64_t need = ballot(count > a.cap - KT) & 0xffffffffull;
@@ -515,8 +547,8 @@ __global__ __launch_bounds__(TileGeom<P>::THREADS) __attribute__((amdgpu_waves_p
                 need &= need - 1;
                 int cnt_q = __shfl(count, q, WAVE);
                 int kc_q = __shfl(kcq, q, WAVE);
-                uint64_t* sq = a.slots + ((size_t)((int64_t)qb * QB + 32 * w + q) * a.S + split) * (size_t)a.cap;
-                const int32_t v_q = a.views ? a.views[(int64_t)qb * QB + 32 * w + q] : a.view;
+                uint64_t* sq = a.slots + ((size_t)(qbase + 32 * w + q) * a.S + split) * (size_t)a.cap;
+                const int32_t v_q = a.views ? a.views[qbase + 32 * w + q] : a.view;
                 const Shrunk sh = shrink_slot(sq, cnt_q, kc_q, hist, death, v_q);
                 if ((l & 31) == q) {
                     count = sh.n;
@@ -524,10 +556,10 @@ __global__ __launch_bounds__(TileGeom<P>::THREADS) __attribute__((amdgpu_waves_p
                 }
             }
         }
-        const int key0 = tile * KT;
+        const int key0 = tile_id(pos) * KT;
         // tiles inside every query's key range skip the per-key range checks
         const bool edge = key0 < a.key_lo || key0 + KT > nl_min;
-        const float* kn = Kn[tile % 3];
+        const float* kn = Kn[pos % 3];
 #pragma unroll
         for (int b = 0; b < NKB; ++b) {
             // block-level test first: one compare and one branch for the 16
@@ -567,12 +599,12 @@ __global__ __launch_bounds__(TileGeom<P>::THREADS) __attribute__((amdgpu_waves_p
         }
     };
 
-    const int n_tiles = tile_end - tile_begin;
+    const int n_tiles = max(0, tile_end - tile_begin);
     const int total_g = n_tiles * n_chunks;
     if (total_g > 0) {
-        ATSNE_LOAD_CHUNK(tile_begin, 0);
-        ATSNE_STORE_CHUNK(0, tile_begin, 0);
-        if (total_g > 1) ATSNE_LOAD_CHUNK(tile_begin + (n_chunks > 1 ? 0 : 1), n_chunks > 1 ? 1 : 0);
+        ATSNE_LOAD_CHUNK(tile_id(tile_begin), 0);
+        ATSNE_STORE_CHUNK(0, tile_begin, tile_id(tile_begin), 0);
+        if (total_g > 1) ATSNE_LOAD_CHUNK(tile_id(tile_begin + (n_chunks > 1 ? 0 : 1)), n_chunks > 1 ? 1 : 0);
         __syncthreads();
     }
     int g = 0;
@@ -593,11 +625,11 @@ __global__ __launch_bounds__(TileGeom<P>::THREADS) __attribute__((amdgpu_waves_p
                 // regs hold chunk g+1; park it in the other buffer, fetch g+2
                 const int c1 = (c + 1 == n_chunks) ? 0 : c + 1;
                 const int t1 = (c + 1 == n_chunks) ? tile + 1 : tile;
-                ATSNE_STORE_CHUNK((g + 1) & 1, t1, c1);
+                ATSNE_STORE_CHUNK((g + 1) & 1, t1, tile_id(t1), c1);
                 if (g + 2 < total_g) {
                     const int c2 = (c1 + 1 == n_chunks) ? 0 : c1 + 1;
                     const int t2 = (c1 + 1 == n_chunks) ? t1 + 1 : t1;
-                    ATSNE_LOAD_CHUNK(t2, c2);
+                    ATSNE_LOAD_CHUNK(tile_id(t2), c2);
                 }
             }
             __syncthreads();
@@ -613,8 +645,8 @@ __global__ __launch_bounds__(TileGeom<P>::THREADS) __attribute__((amdgpu_waves_p
             need &= need - 1;
             int cnt_q = __shfl(count, q, WAVE);
             int kc_q = __shfl(kcq, q, WAVE);
-            uint64_t* sq = a.slots + ((size_t)((int64_t)qb * QB + 32 * w + q) * a.S + split) * (size_t)a.cap;
-            const int32_t v_q = a.views ? a.views[(int64_t)qb * QB + 32 * w + q] : a.view;
+            uint64_t* sq = a.slots + ((size_t)(qbase + 32 * w + q) * a.S + split) * (size_t)a.cap;
+            const int32_t v_q = a.views ? a.views[qbase + 32 * w + q] : a.view;
             const Shrunk sh = shrink_slot(sq, cnt_q, kc_q, hist, death, v_q);
             if ((l & 31) == q) count = sh.n;
         }
@@ -753,6 +785,9 @@ struct SelArgs {
     const int32_t* death;
     const int32_t* views;
     int32_t view;
+    const int32_t* row_blk;  // tile lists: block of each row (NULL: whole key range)
+    const int32_t* blk_t;
+    const int32_t* tl_idx;
     const uint64_t* slots;
     const int32_t* counts;
     int32_t* out_idx;
@@ -926,13 +961,24 @@ __global__ __launch_bounds__(256) void knn_scan(SelArgs a, int keep_extra, int32
         float tau = out_d2[k - 1];
         bool strict = false;
         int cnt = 0;
-        for (int64_t j0 = a.key_lo + w; j0 < nl; j0 += 16) {
+        // key ranges: the row's tile list, or [key_lo, nl); ascending either way
+        const int32_t* tl = nullptr;
+        int n_ranges = 1;
+        if (a.row_blk) {
+            const int bk = a.row_blk[m];
+            tl = a.tl_idx + a.blk_t[bk];
+            n_ranges = a.blk_t[bk + 1] - a.blk_t[bk];
+        }
+        for (int rg = 0; rg < n_ranges; ++rg) {
+        const int64_t r_lo = tl ? (int64_t)tl[rg] * KT : a.key_lo;
+        const int64_t r_hi = tl ? min<int64_t>(r_lo + KT, nl) : nl;
+        for (int64_t j0 = r_lo + w; j0 < r_hi; j0 += 16) {
             float dj[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int64_t j = j0 + 4 * u;
                 float acc = 0.f;
-                if (j < nl) {
+                if (j < r_hi) {
                     const float* xj = a.X + j * a.ld;
                     for (int d = l; d < a.D; d += WAVE) {
                         float tt = xq[d] - xj[d];
@@ -944,7 +990,7 @@ __global__ __launch_bounds__(256) void knn_scan(SelArgs a, int keep_extra, int32
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int64_t j = j0 + 4 * u;
-                const bool pass = j < nl && j != q && key_visible(a.death, j, vq) &&
+                const bool pass = j < r_hi && j != q && key_visible(a.death, j, vq) &&
                                   (strict ? (dj[u] < tau) : (dj[u] <= tau));
                 if (pass) {
                     if (l == 0) reg[cnt] = pack_key(dj[u], (int32_t)j);
@@ -974,6 +1020,7 @@ __global__ __launch_bounds__(256) void knn_scan(SelArgs a, int keep_extra, int32
                 tau = key_dist(kstar);
                 strict = true;
             }
+        }
         }
         if (l == 0) rcount[w] = cnt;
         __syncthreads();
@@ -1218,6 +1265,26 @@ SearchPlan plan_search(int prec, int64_t M, int64_t key_lo, int64_t key_hi, int 
     return p;
 }
 
+SearchPlan plan_list_search(int64_t M, int64_t n_blocks, int k_max, int kc_max, int S) {
+    SearchPlan p;
+    p.qb = qb_of(ATSNE_PREC_FP32);
+    p.M = M;
+    p.k_max = k_max;
+    p.kc_max = kc_max;
+    p.cap = (int)align_up((size_t)(kc_max + KT + std::max(kc_max, 128)), 64);
+    p.MB = (int)std::max<int64_t>(n_blocks, 1);
+    p.S = std::max(1, S);
+    p.tiles_per_split = 1;
+    // slots are indexed by batch row; MB * qb >= M since a block holds at most qb rows
+    Arena a;
+    a.take<uint64_t>((size_t)p.MB * p.qb * p.S * p.cap);
+    a.take<int32_t>((size_t)p.MB * p.qb * p.S);
+    a.take<int32_t>(64);
+    a.take<int32_t>(std::max<int64_t>(M, 1));
+    p.ws_bytes = a.used;
+    return p;
+}
+
 struct SearchWs {
     uint64_t* slots;
     int32_t* counts;
@@ -1265,18 +1332,25 @@ static atsne_status launch_tile(const Corpus& c, const Batch& b, const SearchPla
     t.tile_lo = p.tile_lo;
     t.tile_hi = p.tile_hi;
     t.cap = p.cap;
+    t.blk_q = b.blk_q;
+    t.blk_t = b.blk_t;
+    t.tl_idx = b.tl_idx;
+    if (b.blk_q) t.MB = (int)b.n_blocks;
     t.slots = w.slots;
     t.counts = w.counts;
-    ProfScope ps_(b.tau0 ? "knn_tile_reverse" : "knn_tile", st);
+    ProfScope ps_(b.tau0 ? "knn_tile_reverse" : (b.blk_q ? "knn_tile_list" : "knn_tile"), st);
     const dim3 grid((unsigned)(t.MB * p.S)), block(TileGeom<P>::THREADS);
     if constexpr (P == ATSNE_PREC_FP32) {
-        if (c.death)
-            knn_tile<P, true><<<grid, block, 0, st>>>(t);
+        ATSNE_REQUIRE(!(c.death && b.blk_q), ATSNE_E_UNSUPPORTED, "tile lists with deletion stamps");
+        if (b.blk_q)
+            knn_tile<P, TILE_LIST><<<grid, block, 0, st>>>(t);
+        else if (c.death)
+            knn_tile<P, TILE_VIS><<<grid, block, 0, st>>>(t);
         else
-            knn_tile<P, false><<<grid, block, 0, st>>>(t);
+            knn_tile<P, TILE_PLAIN><<<grid, block, 0, st>>>(t);
     } else {
-        ATSNE_REQUIRE(!c.death, ATSNE_E_UNSUPPORTED, "deletion stamps need the FP32 corpus");
-        knn_tile<P, false><<<grid, block, 0, st>>>(t);
+        ATSNE_REQUIRE(!c.death && !b.blk_q, ATSNE_E_UNSUPPORTED, "deletion stamps and tile lists need the FP32 corpus");
+        knn_tile<P, TILE_PLAIN><<<grid, block, 0, st>>>(t);
     }
     ATSNE_LAUNCH_CHECK();
     return ATSNE_OK;
@@ -1317,6 +1391,9 @@ static SelArgs sel_args(const Corpus& c, const Batch& b, const SearchPlan& p, co
     s.death = c.death;
     s.views = b.views;
     s.view = b.view;
+    s.row_blk = b.row_blk;
+    s.blk_t = b.blk_t;
+    s.tl_idx = b.tl_idx;
     s.slots = w.slots;
     s.counts = w.counts;
     s.out_idx = b.out_idx;

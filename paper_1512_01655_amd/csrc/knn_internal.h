@@ -52,6 +52,15 @@ struct Batch {
     int64_t tau0_stride = 0;      // element stride of tau0 (rows' d_max inside a neighbour table)
     const int32_t* views = nullptr;  // per-row view for deletion visibility; null: view
     int32_t view = 0;
+    // Tile lists (restricted search, FP32): block b holds batch rows
+    // [blk_q[b], blk_q[b+1]) (at most KNN_KT of them) and searches the key
+    // tiles tl_idx[blk_t[b] .. blk_t[b+1]) (ascending); row_blk[m] is the
+    // block of row m.  Null blk_q: every row searches [key_lo, nlim).
+    int64_t n_blocks = 0;
+    const int32_t* blk_q = nullptr;
+    const int32_t* blk_t = nullptr;
+    const int32_t* tl_idx = nullptr;
+    const int32_t* row_blk = nullptr;
     int32_t* out_idx = nullptr;
     float* out_d2 = nullptr;
     uint8_t* out_flags = nullptr;
@@ -87,6 +96,14 @@ atsne_status knn_reverse(const Corpus& c, const Batch& b, const SearchPlan& p, i
 atsne_status calibrate_table(const float* d2, int64_t stride, const int32_t* row_ids, const int32_t* n_rows_dev,
                              int64_t n_rows, int k, float mu, float tol, int max_iter, float* P, float* beta,
                              float* perp, uint8_t* flags, hipStream_t st);
+
+// Ascending 64-bit key sort (radix); tmp holds sort_u64_temp_bytes(n) bytes.
+size_t sort_u64_temp_bytes(int64_t n);
+atsne_status sort_u64(void* tmp, size_t tmp_bytes, const uint64_t* in, uint64_t* out, int64_t n, hipStream_t st);
+
+// Plan a search restricted to per-block tile lists (Batch::blk_q set):
+// M rows in n_blocks blocks, S splits per block.
+SearchPlan plan_list_search(int64_t M, int64_t n_blocks, int k_max, int kc_max, int S);
 
 // Serving-loop data manipulation (Sec. 5.3); resident lists have k entries
 // per row, present entries first, absent ones (index -1, +inf) last.

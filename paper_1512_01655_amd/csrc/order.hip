@@ -20,7 +20,7 @@
 
 #include <rocprim/device/device_radix_sort.hpp>
 
-#include "common.h"
+#include "knn_internal.h"
 #include "wave.h"
 
 namespace atsne {
@@ -104,10 +104,18 @@ __global__ __launch_bounds__(256) void ord_collect(const uint32_t* __restrict__ 
 
 static unsigned blocks(int64_t n) { return (unsigned)std::max<int64_t>(1, ceil_div(n, 256)); }
 
-static size_t sort_temp_bytes(int64_t n) {
+static size_t sort_temp_bytes(int64_t n) { return sort_u64_temp_bytes(n); }
+
+size_t sort_u64_temp_bytes(int64_t n) {
     size_t bytes = 0;
     (void)rocprim::radix_sort_keys(nullptr, bytes, (const uint64_t*)nullptr, (uint64_t*)nullptr, (size_t)n, 0, 64);
-    return bytes;
+    return std::max<size_t>(bytes, 1);
+}
+
+atsne_status sort_u64(void* tmp, size_t tmp_bytes, const uint64_t* in, uint64_t* out, int64_t n, hipStream_t st) {
+    if (n == 0) return ATSNE_OK;
+    ATSNE_HIP(rocprim::radix_sort_keys(tmp, tmp_bytes, in, out, (size_t)n, 0, 64, st));
+    return ATSNE_OK;
 }
 
 struct OrderWs {
@@ -137,8 +145,7 @@ static size_t order_ws(int64_t N, void* base, OrderWs* w) {
 
 static atsne_status sort_and_unpack(OrderWs& w, int64_t n, int32_t* out, hipStream_t st) {
     if (n == 0) return ATSNE_OK;
-    size_t bytes = w.sort_bytes;
-    ATSNE_HIP(rocprim::radix_sort_keys(w.sort_tmp, bytes, w.keys_in, w.keys_out, (size_t)n, 0, 64, st));
+    ATSNE_TRY(sort_u64(w.sort_tmp, w.sort_bytes, w.keys_in, w.keys_out, n, st));
     ord_unpack<<<blocks(n), 256, 0, st>>>(w.keys_out, n, out);
     ATSNE_LAUNCH_CHECK();
     return ATSNE_OK;
