@@ -345,6 +345,10 @@ struct TileArgs {
     const int32_t* views;
     int32_t view;
     int MB, S, tiles_per_split, tile_lo, tile_hi, cap;
+    // the final shrink runs for slots above max(kc, final_keep): a split of a
+    // single tile hands all its keys to the select, whose union threshold is
+    // one parallel pass per row instead of a serial shrink per query here
+    int final_keep;
     // tile lists (restricted search): block b holds rows [blk_q[b], blk_q[b+1])
     // and searches the key tiles tl_idx[blk_t[b] .. blk_t[b+1])
     const int32_t* blk_q;
@@ -637,9 +641,10 @@ __global__ __launch_bounds__(TileGeom<P>::THREADS) __attribute__((amdgpu_waves_p
         epilogue(tile);
     }
 
-    // Final shrink so each slot hands at most kc candidates to the next stage.
+    // Final shrink so each slot hands at most max(kc, final_keep) candidates
+    // to the next stage.
     {
-        uint64_t need = ballot(count > kcq) & 0xffffffffull;
+        uint64_t need = ballot(count > max(kcq, a.final_keep)) & 0xffffffffull;
         while (need) {
             int q = __ffsll((unsigned long long)need) - 1;
             need &= need - 1;
@@ -663,19 +668,51 @@ __global__ __launch_bounds__(TileGeom<P>::THREADS) __attribute__((amdgpu_waves_p
 // ---------------------------------------------------------------------------
 constexpr float TIE_REL = 8e-6f;  // > worst-case relative error of the FP32 direct difference used here
 
-__device__ void finalize_row(const float* __restrict__ X, int64_t ld, int32_t D, const float* __restrict__ xq_g,
-                             int n, int k, int32_t* cj, float* cd, uint64_t* sorted, double* dd,
-                             int32_t* __restrict__ out_idx, float* __restrict__ out_d2, uint8_t* flag_out,
-                             uint8_t extra_flags) {
+// Sort the n candidates (cj, cd) by the key (d, j) into sorted[0, n) by
+// counting ranks (keys are distinct).  Each lane ranks up to four candidates
+// in one pass over the keys, eight keys per step, so the LDS latency is paid
+// once per eight keys.  `tmp` is scratch for n keys.
+__device__ void rank_sort(int n, const int32_t* cj, const float* cd, uint64_t* tmp, uint64_t* sorted) {
     const int l = lane_id();
-    // rank by counting on the 64-bit key (d, j); keys are distinct
-    for (int c = l; c < n; c += WAVE) {
-        uint64_t kc_ = pack_key(cd[c], cj[c]);
-        int r = 0;
-        for (int o = 0; o < n; ++o) r += pack_key(cd[o], cj[o]) < kc_;
-        sorted[r] = kc_;
+    for (int c = l; c < n; c += WAVE) tmp[c] = pack_key(cd[c], cj[c]);
+    wave_sync();
+    for (int c0 = 0; c0 < n; c0 += 4 * WAVE) {
+        uint64_t kc[4];
+        int r[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int c = c0 + l + WAVE * u;
+            kc[u] = c < n ? tmp[c] : ~0ull;
+            r[u] = 0;
+        }
+        int o = 0;
+        for (; o + 8 <= n; o += 8) {
+            uint64_t ko[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) ko[e] = tmp[o + e];
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) r[u] += ko[e] < kc[u] ? 1 : 0;
+        }
+        for (; o < n; ++o) {
+            const uint64_t ko = tmp[o];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) r[u] += ko < kc[u] ? 1 : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (c0 + l + WAVE * u < n) sorted[r[u]] = kc[u];
     }
     wave_sync();
+}
+
+// Write the row from candidates already sorted by rank_sort: FP64 re-rank
+// when the k-th/(k+1)-th gap is below FP32 resolution.
+__device__ void finalize_sorted(const float* __restrict__ X, int64_t ld, int32_t D, const float* __restrict__ xq_g,
+                                int n, int k, const uint64_t* sorted, double* dd, int32_t* __restrict__ out_idx,
+                                float* __restrict__ out_d2, uint8_t* flag_out, uint8_t extra_flags) {
+    const int l = lane_id();
     uint8_t fl = extra_flags;
     bool tie = false;
     if (n > k) {
@@ -684,7 +721,35 @@ __device__ void finalize_row(const float* __restrict__ X, int64_t ld, int32_t D,
     }
     if (tie) {
         // FP64 direct differences for every candidate, then rank by (d64, j).
-        for (int c = 0; c < n; ++c) {
+        // Eight candidates at a time keep eight row loads in flight; each
+        // candidate's sum is the same arithmetic whatever the group size.
+        int c = 0;
+        for (; c + 8 <= n; c += 8) {
+            const float* xr[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) xr[e] = X + (int64_t)key_index(sorted[c + e]) * ld;
+            double acc[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) acc[e] = 0.0;
+            for (int d = l; d < D; d += WAVE) {
+                const double q = (double)xq_g[d];
+                float xv[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) xv[e] = xr[e][d];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const double t = q - (double)xv[e];
+                    acc[e] = fma(t, t, acc[e]);
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) acc[e] = wave_sum(acc[e]);
+            if (l == 0) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) dd[c + e] = acc[e];
+            }
+        }
+        for (; c < n; ++c) {
             const float* xc = X + (int64_t)key_index(sorted[c]) * ld;
             double acc = 0.0;
             for (int d = l; d < D; d += WAVE) {
@@ -695,18 +760,44 @@ __device__ void finalize_row(const float* __restrict__ X, int64_t ld, int32_t D,
             if (l == 0) dd[c] = acc;
         }
         wave_sync();
-        for (int c = l; c < n; c += WAVE) {
-            double dc = dd[c];
-            int32_t jc = key_index(sorted[c]);
-            int r = 0;
-            for (int o = 0; o < n; ++o) {
-                double dox = dd[o];
-                int32_t jo = key_index(sorted[o]);
-                r += (dox < dc) || (dox == dc && jo < jc);
+        // rank by (d64, j), four candidates per lane per pass over the keys
+        for (int c0 = 0; c0 < n; c0 += 4 * WAVE) {
+            double dc[4];
+            int32_t jc[4];
+            int r[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int cc = c0 + l + WAVE * u;
+                dc[u] = cc < n ? dd[cc] : 0.0;
+                jc[u] = cc < n ? key_index(sorted[cc]) : 0;
+                r[u] = 0;
             }
-            if (r < k) {
-                out_idx[r] = jc;
-                out_d2[r] = (float)dc;
+            int o = 0;
+            for (; o + 4 <= n; o += 4) {
+                double dox[4];
+                int32_t jo[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    dox[e] = dd[o + e];
+                    jo[e] = key_index(sorted[o + e]);
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) r[u] += (dox[e] < dc[u]) || (dox[e] == dc[u] && jo[e] < jc[u]);
+            }
+            for (; o < n; ++o) {
+                const double dox = dd[o];
+                const int32_t jo = key_index(sorted[o]);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) r[u] += (dox < dc[u]) || (dox == dc[u] && jo < jc[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (c0 + l + WAVE * u < n && r[u] < k) {
+                    out_idx[r[u]] = jc[u];
+                    out_d2[r[u]] = (float)dc[u];
+                }
             }
         }
         fl |= ATSNE_FLAG_FP64_RERANKED;
@@ -719,12 +810,49 @@ __device__ void finalize_row(const float* __restrict__ X, int64_t ld, int32_t D,
     if (flag_out && l == 0) *flag_out = fl;
 }
 
+// Sort the candidates (rank_sort, with dd as its scratch) and write the row.
+__device__ void finalize_row(const float* __restrict__ X, int64_t ld, int32_t D, const float* __restrict__ xq_g,
+                             int n, int k, int32_t* cj, float* cd, uint64_t* sorted, double* dd,
+                             int32_t* __restrict__ out_idx, float* __restrict__ out_d2, uint8_t* flag_out,
+                             uint8_t extra_flags) {
+    rank_sort(n, cj, cd, reinterpret_cast<uint64_t*>(dd), sorted);
+    finalize_sorted(X, ld, D, xq_g, n, k, sorted, dd, out_idx, out_d2, flag_out, extra_flags);
+}
+
 // Exact FP32 direct-difference distances from query q to the n candidates in
 // cj (wave-parallel over dimensions, butterfly reduction), into cd.
 __device__ void direct_distances(const float* __restrict__ X, int64_t ld, int32_t D, const float* __restrict__ xq,
                                  int n, const int32_t* cj, float* cd) {
     const int l = lane_id();
     int c = 0;
+    // eight candidates at a time keep eight row loads in flight per lane;
+    // every candidate's sum (lane-strided partials, then the butterfly) is
+    // the same arithmetic whatever the group size
+    for (; c + 8 <= n; c += 8) {
+        const float* xr[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) xr[e] = X + (int64_t)cj[c + e] * ld;
+        float acc[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) acc[e] = 0.f;
+        for (int d = l; d < D; d += WAVE) {
+            const float q = xq[d];
+            float xv[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) xv[e] = xr[e][d];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const float t = q - xv[e];
+                acc[e] = fmaf(t, t, acc[e]);
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) acc[e] = wave_sum(acc[e]);
+        if (l == 0) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) cd[c + e] = acc[e];
+        }
+    }
     for (; c + 4 <= n; c += 4) {
         const float* x0 = X + (int64_t)cj[c] * ld;
         const float* x1 = X + (int64_t)cj[c + 1] * ld;
@@ -815,14 +943,24 @@ __device__ uint64_t union_threshold(Each each, int take, int total, uint32_t* hi
 }
 
 // knn_select: one wave (workgroup of 64) per query row.
+constexpr int SEL_RK = 32;     // union keys per lane held in registers (2048 per row)
+constexpr int SEL_MAX_S = 64;  // splits whose prefix counts fit the LDS table
+
 // LDS of knn_select for up to kcap candidates (sized at launch).
 __host__ __device__ constexpr size_t select_lds_bytes(int kcap) {
-    return 256 * 4 + (size_t)kcap * (8 + 8 + 4 + 4) + 16;
+    return (256 * 4 + (size_t)kcap * (8 + 8 + 4 + 4) + 16 + 15) & ~(size_t)15;
+}
+constexpr int SEL_ROWS = 4;  // at most this many rows (one wave each) per workgroup
+// rows per workgroup for a candidate capacity: keep the dynamic LDS within 64 KiB
+static inline int sel_rows(int kcap) {
+    return (int)std::max<size_t>(1, std::min<size_t>(SEL_ROWS, 65536 / select_lds_bytes(kcap)));
 }
 
 template <int P>
-__global__ __launch_bounds__(64) void knn_select(SelArgs a, int kcap) {
-    extern __shared__ __align__(16) unsigned char sel_lds[];
+__global__ __launch_bounds__(64 * SEL_ROWS) void knn_select(SelArgs a, int kcap) {
+    extern __shared__ __align__(16) unsigned char sel_lds_all[];
+    const int w = threadIdx.x >> 6;
+    unsigned char* sel_lds = sel_lds_all + (size_t)w * select_lds_bytes(kcap);
     double* dd = reinterpret_cast<double*>(sel_lds);
     uint64_t* sorted = reinterpret_cast<uint64_t*>(dd + kcap);
     uint32_t* hist = reinterpret_cast<uint32_t*>(sorted + kcap);
@@ -830,8 +968,8 @@ __global__ __launch_bounds__(64) void knn_select(SelArgs a, int kcap) {
     float* cd = reinterpret_cast<float*>(cj + kcap);
     int32_t& ncand = *reinterpret_cast<int32_t*>(cd + kcap);
     const int l = lane_id();
-    const int64_t m = blockIdx.x;
-    if (m >= a.M) return;
+    const int64_t m = (int64_t)blockIdx.x * (blockDim.x >> 6) + w;
+    if (m >= a.M) return;  // waves are independent: no workgroup barrier below
     const int64_t q = load_qid(a.qids, a.m0, m);
     const int64_t nl = a.nlims ? (int64_t)a.nlims[m] : a.nlim;
     const int k = a.ks ? a.ks[m] : a.k;
@@ -855,26 +993,67 @@ __global__ __launch_bounds__(64) void knn_select(SelArgs a, int kcap) {
         }
     }
     const int take = min(kc, total);
-    auto each = [&](auto f) {
-        for (int s = 0; s < a.S; ++s) {
-            const uint64_t* sl = base + (size_t)s * a.cap;
-            const int c = cnt[s];
-            for (int i = l; i < c; i += WAVE) {
-                const uint64_t key = sl[i];
-                if (!a.death || a.death[key_index(key)] >= vq) f(key);
+    // threshold of the union, then its candidates into cj
+    auto select_union = [&](auto each) {
+        const uint64_t ks = union_threshold(each, take, total, hist);
+        if (l == 0) ncand = 0;
+        wave_sync();
+        each([&](uint64_t key) {
+            if (key <= ks) {
+                int p = atomicAdd(&ncand, 1);
+                cj[p] = key_index(key);
+            }
+        });
+        wave_sync();
+        return ks;
+    };
+    uint64_t kstar;
+    if (!a.death && total <= SEL_RK * WAVE) {
+        // small unions are read once into registers, every load in flight
+        // together, so the radix passes run without memory latency
+        __shared__ int32_t spre_all[SEL_ROWS][SEL_MAX_S + 1];
+        int32_t* spre = spre_all[w];
+        if (a.S <= SEL_MAX_S) {
+            int c = l < a.S ? cnt[l] : 0;
+            const int incl = (int)wave_incl_scan((uint32_t)c);
+            if (l < a.S) spre[l + 1] = incl;
+            if (l == 0) spre[0] = 0;
+            wave_sync();
+        }
+        uint64_t rk[SEL_RK];
+        int sp = 0;
+#pragma unroll
+        for (int u = 0; u < SEL_RK; ++u) {
+            const int pos = l + WAVE * u;
+            rk[u] = ~0ull;
+            if (pos < total) {
+                if (a.S <= SEL_MAX_S) {
+                    while (pos >= spre[sp + 1]) ++sp;
+                    rk[u] = base[(size_t)sp * a.cap + (pos - spre[sp])];
+                } else {
+                    int s = 0, b0 = 0;
+                    while (pos >= b0 + cnt[s]) b0 += cnt[s++];
+                    rk[u] = base[(size_t)s * a.cap + (pos - b0)];
+                }
             }
         }
-    };
-    const uint64_t kstar = union_threshold(each, take, total, hist);
-    if (l == 0) ncand = 0;
-    wave_sync();
-    each([&](uint64_t key) {
-        if (key <= kstar) {
-            int p = atomicAdd(&ncand, 1);
-            cj[p] = key_index(key);
-        }
-    });
-    wave_sync();
+        kstar = select_union([&](auto f) {
+#pragma unroll
+            for (int u = 0; u < SEL_RK; ++u)
+                if (l + WAVE * u < total) f(rk[u]);
+        });
+    } else {
+        kstar = select_union([&](auto f) {
+            for (int s = 0; s < a.S; ++s) {
+                const uint64_t* sl = base + (size_t)s * a.cap;
+                const int c = cnt[s];
+                for (int i = l; i < c; i += WAVE) {
+                    const uint64_t key = sl[i];
+                    if (!a.death || a.death[key_index(key)] >= vq) f(key);
+                }
+            }
+        });
+    }
     const int n = ncand;
     const float* xq = a.X + q * a.ld;
     direct_distances(a.X, a.ld, a.D, xq, n, cj, cd);
@@ -886,6 +1065,7 @@ __global__ __launch_bounds__(64) void knn_select(SelArgs a, int kcap) {
     }
 
     uint8_t extra = 0;
+    if (n >= k) rank_sort(n, cj, cd, reinterpret_cast<uint64_t*>(dd), sorted);
     const int64_t n_valid = max<int64_t>(0, nl - a.key_lo) - ((q >= a.key_lo && q < nl) ? 1 : 0);
     if (P == ATSNE_PREC_FP32 && take < n_valid && n >= k) {
         // Certificate: every non-candidate j has d'_j >= d'(kstar), so its
@@ -894,15 +1074,7 @@ __global__ __launch_bounds__(64) void knn_select(SelArgs a, int kcap) {
         // error), the candidates hold the true k+1 nearest and the row's
         // ranking, tie decision included, is that of a full scan.
         const int rk = n > k ? k : k - 1;
-        for (int c = l; c < n; c += WAVE) {
-            uint64_t kc_ = pack_key(cd[c], cj[c]);
-            int r = 0;
-            for (int o = 0; o < n; ++o) r += pack_key(cd[o], cj[o]) < kc_;
-            if (r == rk) sorted[0] = kc_;
-        }
-        wave_sync();
-        const float dk = key_dist(sorted[0]);
-        wave_sync();
+        const float dk = key_dist(sorted[rk]);
         const float nq = a.norms[q];
         const float nmax = nl > 0 ? a.pmax[nl - 1] : 0.0f;
         const float dthr = key_dist(kstar);
@@ -916,8 +1088,8 @@ __global__ __launch_bounds__(64) void knn_select(SelArgs a, int kcap) {
         }
     }
     if (n >= k)
-        finalize_row(a.X, a.ld, a.D, xq, n, k, cj, cd, sorted, dd, out_idx, out_d2,
-                     a.out_flags ? a.out_flags + m : nullptr, extra);
+        finalize_sorted(a.X, a.ld, a.D, xq, n, k, sorted, dd, out_idx, out_d2,
+                        a.out_flags ? a.out_flags + m : nullptr, extra);
 }
 
 // knn_scan: exact FP32 linear scan for rows whose candidate margin was not
@@ -1332,6 +1504,7 @@ static atsne_status launch_tile(const Corpus& c, const Batch& b, const SearchPla
     t.tile_lo = p.tile_lo;
     t.tile_hi = p.tile_hi;
     t.cap = p.cap;
+    t.final_keep = (!b.blk_q && !b.tau0 && p.tiles_per_split == 1) ? KT : 0;
     t.blk_q = b.blk_q;
     t.blk_t = b.blk_t;
     t.tl_idx = b.tl_idx;
@@ -1415,16 +1588,18 @@ atsne_status knn_search(const Corpus& c, const Batch& b, const SearchPlan& p, vo
     {
         ProfScope ps_("knn_select", st);
         const int kcap = p.kc_max;
-        const size_t lds = select_lds_bytes(kcap);
+        const int rows = sel_rows(kcap);
+        const size_t lds = rows * select_lds_bytes(kcap);
+        const dim3 sel_grid((unsigned)ceil_div(b.M, rows));
         switch (c.prec) {
             case ATSNE_PREC_FP32:
-                knn_select<ATSNE_PREC_FP32><<<dim3((unsigned)b.M), dim3(64), lds, st>>>(s, kcap);
+                knn_select<ATSNE_PREC_FP32><<<sel_grid, dim3(64 * rows), lds, st>>>(s, kcap);
                 break;
             case ATSNE_PREC_BF16:
-                knn_select<ATSNE_PREC_BF16><<<dim3((unsigned)b.M), dim3(64), lds, st>>>(s, kcap);
+                knn_select<ATSNE_PREC_BF16><<<sel_grid, dim3(64 * rows), lds, st>>>(s, kcap);
                 break;
             default:
-                knn_select<ATSNE_PREC_FP8_E4M3><<<dim3((unsigned)b.M), dim3(64), lds, st>>>(s, kcap);
+                knn_select<ATSNE_PREC_FP8_E4M3><<<sel_grid, dim3(64 * rows), lds, st>>>(s, kcap);
         }
         ATSNE_LAUNCH_CHECK();
     }
