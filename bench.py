@@ -35,6 +35,9 @@ def parse():
     ap.add_argument("--no-bf16", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--path-only", action="store_true",
+                    help="only the FP32 and BF16 steps (no approximate, attractive, ordering, serving legs): the "
+                         "command the kernel-trace profile runs")
     ap.add_argument("--profile-kernel", default=None, choices=["fp32", "bf16", "fp8"],
                     help="profiling mode: one warm-up and one timed kNN at this precision, then a 1 GiB device "
                          "copy (the reference kernel for scaling HBM byte counters); prints the launch shapes")
@@ -412,10 +415,13 @@ def main():
             "agree_with_fp32_rows": float((rb["idx"] == r["idx"]).all(1).float().mean().item()),
         }
         log("bf16: %.1f points/s (x%.2f)" % (vb, vb / value))
-    if not a.no_serve and a.workload == "imagelike":
+    if not (a.no_serve or a.path_only) and a.workload == "imagelike":
         log("serve: Poisson stream at %.0f req/s ..." % a.serve_rate)
         line["serve"] = serve_load(A, torch, X, a.serve_rate, a.serve_requests + 10, 10)
         log("serve: p50 %.1f ms, p99 %.1f ms" % (line["serve"]["p50_ms"], line["serve"]["p99_ms"]))
+    if a.path_only:
+        print(json.dumps(line), flush=True)
+        return
     if a.workload == "imagelike":
         log("precision-controlled path (rho = 0.9) ...")
         line["approx_rho"] = approx_leg(A, torch, Xt, mu, k, r["idx"], value)

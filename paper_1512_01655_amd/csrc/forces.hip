@@ -20,6 +20,7 @@
 namespace atsne {
 
 constexpr int ATTR_G = 16;  // lanes per row
+constexpr int ATTR_U = 4;   // entries per lane in flight
 
 template <int DIMS>
 __global__ __launch_bounds__(256) void attractive_rows(const int64_t* __restrict__ row_ptr,
@@ -39,20 +40,40 @@ __global__ __launch_bounds__(256) void attractive_rows(const int64_t* __restrict
     }
     const int64_t e0 = row_ptr[i];
     const int64_t e1 = min(row_ptr[i + 1], nnz);
-    for (int64_t e = e0 + g; e < e1; e += ATTR_G) {
-        const int32_t j = col[e];
-        if ((uint64_t)j >= (uint64_t)N) continue;  // malformed entry: skipped
-        const float p = val[e];
-        float diff[DIMS];
-        float d2 = 0.f;
+    // ATTR_U entries per lane per step: their column loads, then their
+    // embedding gathers, are all in flight together
+    for (int64_t eb = e0 + g; eb < e1; eb += ATTR_G * ATTR_U) {
+        int32_t j[ATTR_U];
+        float p[ATTR_U];
 #pragma unroll
-        for (int d = 0; d < DIMS; ++d) {
-            diff[d] = yi[d] - Y[(int64_t)j * DIMS + d];
-            d2 = fmaf(diff[d], diff[d], d2);
+        for (int u = 0; u < ATTR_U; ++u) {
+            const int64_t e = eb + (int64_t)ATTR_G * u;
+            const bool ok = e < e1;
+            j[u] = ok ? col[e] : -1;
+            p[u] = ok ? val[e] : 0.f;
         }
-        const float w = p / (1.0f + d2);
+        float yj[ATTR_U][DIMS];
 #pragma unroll
-        for (int d = 0; d < DIMS; ++d) acc[d] = fmaf(w, diff[d], acc[d]);
+        for (int u = 0; u < ATTR_U; ++u) {
+            const bool ok = (uint64_t)j[u] < (uint64_t)N;  // malformed or padding entry: no force
+            if (!ok) p[u] = 0.f;
+            const int64_t jj = ok ? (int64_t)j[u] : i;
+#pragma unroll
+            for (int d = 0; d < DIMS; ++d) yj[u][d] = Y[jj * DIMS + d];
+        }
+#pragma unroll
+        for (int u = 0; u < ATTR_U; ++u) {
+            float diff[DIMS];
+            float d2 = 0.f;
+#pragma unroll
+            for (int d = 0; d < DIMS; ++d) {
+                diff[d] = yi[d] - yj[u][d];
+                d2 = fmaf(diff[d], diff[d], d2);
+            }
+            const float w = p[u] / (1.0f + d2);
+#pragma unroll
+            for (int d = 0; d < DIMS; ++d) acc[d] = fmaf(w, diff[d], acc[d]);
+        }
     }
 #pragma unroll
     for (int d = 0; d < DIMS; ++d) {

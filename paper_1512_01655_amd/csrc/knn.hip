@@ -46,6 +46,7 @@ struct TileGeom {
     static constexpr int QB = 32 * WAVES;  // queries per workgroup
     static constexpr int WPE = P == ATSNE_PREC_FP8_E4M3 ? 1 : 2;
 };
+constexpr int KNN_XCDS = 8;  // accelerator complex dies; workgroups go round-robin over them
 __host__ __device__ constexpr int qb_of(int prec) { return prec == ATSNE_PREC_FP8_E4M3 ? 128 : 256; }
 constexpr int KT = KNN_KT;      // keys per tile (8 MFMA blocks of 32)
 constexpr int NKB = KT / 32;    // key blocks per tile
@@ -391,8 +392,15 @@ __global__ __launch_bounds__(TileGeom<P>::THREADS) __attribute__((amdgpu_waves_p
     const int w = t >> 6;
     constexpr bool VIS = MODE == TILE_VIS;
     constexpr bool LIST = MODE == TILE_LIST;
-    const int qb = blockIdx.x % a.MB;
-    const int split = blockIdx.x / a.MB;
+    // XCD-aware order: workgroup b is dispatched to XCD b % 8, and each XCD
+    // gets a contiguous run of (query block, split) tasks with the split
+    // fastest, so the workgroups resident on one XCD share a few query blocks
+    // and the same key tiles through its L2.
+    const int n_tasks = a.MB * a.S;
+    const int xcd = (int)(blockIdx.x % KNN_XCDS), jx = (int)(blockIdx.x / KNN_XCDS);
+    const int task = xcd * (n_tasks / KNN_XCDS) + min(xcd, n_tasks % KNN_XCDS) + jx;
+    const int qb = task / a.S;
+    const int split = task % a.S;
     // this block's query rows and this split's positions in its tile sequence
     int64_t qbase, qend;
     int tile_begin, tile_end;
