@@ -172,6 +172,14 @@ def precision_eq9(torch, approx, exact, chunk=4096):
     return hits / float(exact.numel())
 
 
+def max_dp_same_rows(torch, rb, r):
+    """max |P_bf16 - P_fp32| over rows whose neighbour lists are identical (same order)."""
+    same = (rb["idx"] == r["idx"]).all(1)
+    if not bool(same.any()):
+        return None
+    return float((rb["P"][same] - r["P"][same]).abs().max().item())
+
+
 def approx_leg(A, torch, Xt, mu, k, exact_idx, exact_value, rho=0.9, C=256, iters=8, steps=5, seed=11):
     """Precision-controlled path: cluster-pruned kNN with n_probe fitted to rho
     on 16 sample clusters, then calibration and symmetrisation.  Precision
@@ -413,6 +421,9 @@ def main():
                          "unit": "TFLOP/s", "frac": round(ach_b / PEAK["bf16"], 4),
                          "traffic": measured_traffic(a.workload, "bf16")},
             "agree_with_fp32_rows": float((rb["idx"] == r["idx"]).all(1).float().mean().item()),
+            # against the exact FP32 path, which matches the FP64 oracle within the tie rule
+            "recall_vs_exact": round(precision_eq9(torch, rb["idx"], r["idx"]), 6),
+            "max_abs_dP_vs_exact_same_rows": max_dp_same_rows(torch, rb, r),
         }
         log("bf16: %.1f points/s (x%.2f)" % (vb, vb / value))
     if not (a.no_serve or a.path_only) and a.workload == "imagelike":

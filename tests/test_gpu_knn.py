@@ -130,5 +130,34 @@ def test_knn_bf16_recall_config2(A, ora):
     rows = np.random.default_rng(8).choice(X.shape[0], size=200, replace=False).astype(np.int32)
     o_idx, o_d2, o_nx = ora.knn(X, 90, query_ids=rows)
     rec = O.recall(g_idx[rows], o_idx)
-    say("    bf16 recall on 200 rows: %.5f" % rec)
-    assert rec >= 0.999
+    import torch
+
+    P, beta, perp, fl = A.calibrate_p(torch.from_numpy(g_d2[rows]).cuda(), 30.0)
+    o_P, _, _, _ = ora.calibrate(o_d2, 30.0)
+    same = np.array([set(a.tolist()) == set(b.tolist()) for a, b in zip(g_idx[rows], o_idx)])
+    dP = parity.check_p_rows(g_idx[rows][same], P.cpu().numpy()[same], o_idx[same], o_P[same], o_d2[same],
+                             o_nx[same], tol=1.0)
+    say("    bf16 recall on 200 rows: %.5f; max |dP| on the %d rows with the exact set: %.2e" % (rec, same.sum(), dP))
+    assert rec >= 0.999 and dP <= parity.P_TOL
+
+
+def test_knn_fp8_config4_sampled(A, ora):
+    """FP8 e4m3 contraction with per-row scales at N = 10^6, D = 128, k = 150,
+    300 candidates re-ranked in FP32: recall and max |dP| against the FP64
+    oracle on a seeded sample of 500 query rows searched over the full corpus."""
+    import torch
+
+    X = datagen.mixture_anisotropic()
+    N, k, kc, mu = X.shape[0], 150, 300, 50.0
+    g_idx, g_d2, g_fl = run_knn(A, X, k, prec="fp8", kc=kc)
+    rows = np.random.default_rng(9).choice(N, size=500, replace=False).astype(np.int32)
+    o_idx, o_d2, o_nx = ora.knn(X, k, query_ids=rows)
+    rec = O.recall(g_idx[rows], o_idx)
+    P, beta, perp, fl = A.calibrate_p(torch.from_numpy(g_d2[rows]).cuda(), mu)
+    o_P, _, _, _ = ora.calibrate(o_d2, mu)
+    same = np.array([set(a.tolist()) == set(b.tolist()) for a, b in zip(g_idx[rows], o_idx)])
+    dP = parity.check_p_rows(g_idx[rows][same], P.cpu().numpy()[same], o_idx[same], o_P[same], o_d2[same],
+                             o_nx[same], tol=1.0)
+    say("    fp8 config4 sample: recall %.5f, rows with the exact set %d/500, max |dP| on them %.2e" % (
+        rec, int(same.sum()), dP))
+    assert rec >= 0.995 and dP <= parity.P_TOL
