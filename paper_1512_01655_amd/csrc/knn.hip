@@ -38,12 +38,16 @@ typedef int i32x8 __attribute__((ext_vector_type(8)));
 // Workgroup geometry per contraction type: FP32 and BF16 run 8 waves (256
 // queries x 256 keys, two waves per SIMD so one wave's epilogue and LDS
 // waits hide behind the other's MFMAs); FP8 keeps 4 waves (128 x 256) at one
-// wave per SIMD, where its scaled MFMAs fit the 512-register budget.
-template <int P>
+// wave per SIMD, where its scaled MFMAs fit the 512-register budget.  The
+// small geometry (FP32/BF16, 4 waves, 128 queries x 128 keys, two
+// workgroups per CU) gives small problems four times as many workgroups.
+template <int P, bool SMALL = false>
 struct TileGeom {
-    static constexpr int WAVES = P == ATSNE_PREC_FP8_E4M3 ? 4 : 8;
+    static constexpr int WAVES = (SMALL || P == ATSNE_PREC_FP8_E4M3) ? 4 : 8;
     static constexpr int THREADS = 64 * WAVES;
     static constexpr int QB = 32 * WAVES;  // queries per workgroup
+    static constexpr int KT = SMALL ? 128 : 256;  // keys per tile
+    static constexpr int NKB = KT / 32;          // MFMA key blocks per tile
     static constexpr int WPE = P == ATSNE_PREC_FP8_E4M3 ? 1 : 2;
 };
 constexpr int KNN_XCDS = 8;  // accelerator complex dies; workgroups go round-robin over them
@@ -371,11 +375,14 @@ __device__ __forceinline__ bool key_visible(const int32_t* death, int64_t j, int
     return !death || death[j] >= view;
 }
 
-template <int P, int MODE>
-__global__ __launch_bounds__(TileGeom<P>::THREADS) __attribute__((amdgpu_waves_per_eu(TileGeom<P>::WPE, TileGeom<P>::WPE))) void knn_tile(TileArgs a) {
-    constexpr int QB = TileGeom<P>::QB;
-    constexpr int TILE_WAVES = TileGeom<P>::WAVES;
-    constexpr int TT = TileGeom<P>::THREADS;
+template <int P, int MODE, bool SMALL>
+__global__ __launch_bounds__((TileGeom<P, SMALL>::THREADS)) __attribute__((amdgpu_waves_per_eu(TileGeom<P, SMALL>::WPE, TileGeom<P, SMALL>::WPE))) void knn_tile(TileArgs a) {
+    using G = TileGeom<P, SMALL>;
+    constexpr int QB = G::QB;
+    constexpr int KT = G::KT;
+    constexpr int NKB = G::NKB;
+    constexpr int TILE_WAVES = G::WAVES;
+    constexpr int TT = G::THREADS;
     constexpr int RSTEP = TT / 8;  // rows between one thread's staged units
     // double-buffered tiles: one barrier per chunk, the next chunk's global
     // loads in flight while this chunk's MFMAs run
@@ -384,7 +391,7 @@ __global__ __launch_bounds__(TileGeom<P>::THREADS) __attribute__((amdgpu_waves_p
     // per-tile norms/scales: three buffers, because a tile's epilogue runs
     // after the barrier that lets faster waves stage the following tiles
     __shared__ float Kn[3][KT];
-    __shared__ float Ksc[3][KT];
+    __shared__ float Ksc[3][P == ATSNE_PREC_FP8_E4M3 ? KT : 1];
     __shared__ uint32_t hist_all[TILE_WAVES][256];
 
     const int t = threadIdx.x;
@@ -481,7 +488,7 @@ __global__ __launch_bounds__(TileGeom<P>::THREADS) __attribute__((amdgpu_waves_p
         pk1 = kb_[kstep_];                                                                           \
         pk2 = kb_[2 * kstep_];                                                                       \
         pk3 = kb_[3 * kstep_];                                                                       \
-        if (RSTEP == 32) {                                                                           \
+        if (KT / RSTEP == 8) {                                                                       \
             pk4 = kb_[4 * kstep_];                                                                   \
             pk5 = kb_[5 * kstep_];                                                                   \
             pk6 = kb_[6 * kstep_];                                                                   \
@@ -500,7 +507,7 @@ __global__ __launch_bounds__(TileGeom<P>::THREADS) __attribute__((amdgpu_waves_p
         ks_[RSTEP * ROW_UNITS] = pk1;                                                                \
         ks_[2 * RSTEP * ROW_UNITS] = pk2;                                                            \
         ks_[3 * RSTEP * ROW_UNITS] = pk3;                                                            \
-        if (RSTEP == 32) {                                                                           \
+        if (KT / RSTEP == 8) {                                                                       \
             ks_[4 * RSTEP * ROW_UNITS] = pk4;                                                        \
             ks_[5 * RSTEP * ROW_UNITS] = pk5;                                                        \
             ks_[6 * RSTEP * ROW_UNITS] = pk6;                                                        \
@@ -513,7 +520,7 @@ __global__ __launch_bounds__(TileGeom<P>::THREADS) __attribute__((amdgpu_waves_p
         qs_[3 * RSTEP * ROW_UNITS] = pq3;                                                            \
         if ((C) == 0 && t < KT) {                                                                    \
             Kn[(POS) % 3][t] = a.norms[(int64_t)(TILE) * KT + t];                                   \
-            if (P == ATSNE_PREC_FP8_E4M3) Ksc[(POS) % 3][t] = a.scales[(int64_t)(TILE) * KT + t];   \
+            if constexpr (P == ATSNE_PREC_FP8_E4M3) Ksc[(POS) % 3][t] = a.scales[(int64_t)(TILE) * KT + t]; \
         }                                                                                            \
     } while (0)
 
@@ -621,7 +628,7 @@ __global__ __launch_bounds__(TileGeom<P>::THREADS) __attribute__((amdgpu_waves_p
     }
     int g = 0;
     for (int tile = tile_begin; tile < tile_end; ++tile) {
-        if (P == ATSNE_PREC_FP8_E4M3) {
+        if constexpr (P == ATSNE_PREC_FP8_E4M3) {
 #pragma unroll
             for (int b = 0; b < NKB; ++b) ksc_e8[b] = e8m0_of(Ksc[tile % 3][32 * b + (l & 31)]);
         } else {
@@ -1421,14 +1428,25 @@ atsne_status corpus_prep(const Corpus& c, int64_t r0, int64_t r1, int64_t n_live
     return ATSNE_OK;
 }
 
-SearchPlan plan_search(int prec, int64_t M, int64_t key_lo, int64_t key_hi, int k_max, int kc_max, int s_max) {
+SearchPlan plan_search(int prec, int64_t M, int64_t key_lo, int64_t key_hi, int k_max, int kc_max, int s_max,
+                       bool allow_small) {
     SearchPlan p;
     p.qb = qb_of(prec);
     p.M = M;
     p.k_max = k_max;
     p.kc_max = kc_max;
-    p.tile_lo = (int)(key_lo / KT);
-    p.tile_hi = (int)ceil_div(key_hi, KT);
+    // small problems (fewer (query block, key tile) pairs than two per CU in
+    // the large geometry) take the 128 x 128 geometry: four times the workgroups
+    if (allow_small && prec != ATSNE_PREC_FP8_E4M3 && key_lo % 128 == 0) {
+        const int64_t pairs = ceil_div(std::max<int64_t>(M, 1), p.qb) * ceil_div(std::max<int64_t>(key_hi - key_lo, 1), KT);
+        if (pairs < 2 * (int64_t)device_cu_count()) {
+            p.small = true;
+            p.qb = TileGeom<ATSNE_PREC_FP32, true>::QB;
+            p.kt = TileGeom<ATSNE_PREC_FP32, true>::KT;
+        }
+    }
+    p.tile_lo = (int)(key_lo / p.kt);
+    p.tile_hi = (int)ceil_div(key_hi, p.kt);
     const int total_tiles = std::max(1, p.tile_hi - p.tile_lo);
     p.cap = (int)align_up((size_t)(kc_max + KT + std::max(kc_max, 128)), 64);
     p.MB = (int)ceil_div(std::max<int64_t>(M, 1), p.qb);
@@ -1506,13 +1524,13 @@ static atsne_status launch_tile(const Corpus& c, const Batch& b, const SearchPla
     t.death = c.death;
     t.views = b.views;
     t.view = b.view;
-    t.MB = (int)ceil_div(b.M, TileGeom<P>::QB);
+    t.MB = (int)ceil_div(b.M, p.qb);
     t.S = p.S;
     t.tiles_per_split = p.tiles_per_split;
     t.tile_lo = p.tile_lo;
     t.tile_hi = p.tile_hi;
     t.cap = p.cap;
-    t.final_keep = (!b.blk_q && !b.tau0 && p.tiles_per_split == 1) ? KT : 0;
+    t.final_keep = (!b.blk_q && !b.tau0 && p.tiles_per_split == 1) ? p.kt : 0;
     t.blk_q = b.blk_q;
     t.blk_t = b.blk_t;
     t.tl_idx = b.tl_idx;
@@ -1520,18 +1538,24 @@ static atsne_status launch_tile(const Corpus& c, const Batch& b, const SearchPla
     t.slots = w.slots;
     t.counts = w.counts;
     ProfScope ps_(b.tau0 ? "knn_tile_reverse" : (b.blk_q ? "knn_tile_list" : "knn_tile"), st);
-    const dim3 grid((unsigned)(t.MB * p.S)), block(TileGeom<P>::THREADS);
-    if constexpr (P == ATSNE_PREC_FP32) {
+    const dim3 grid((unsigned)(t.MB * p.S));
+    if (p.small) {
+        ATSNE_REQUIRE(!c.death && !b.blk_q && !b.tau0 && P != ATSNE_PREC_FP8_E4M3, ATSNE_E_UNSUPPORTED,
+                      "the small geometry serves the plain search only");
+        if constexpr (P != ATSNE_PREC_FP8_E4M3)
+            knn_tile<P, TILE_PLAIN, true><<<grid, dim3(TileGeom<P, true>::THREADS), 0, st>>>(t);
+    } else if constexpr (P == ATSNE_PREC_FP32) {
+        const dim3 block(TileGeom<P>::THREADS);
         ATSNE_REQUIRE(!(c.death && b.blk_q), ATSNE_E_UNSUPPORTED, "tile lists with deletion stamps");
         if (b.blk_q)
-            knn_tile<P, TILE_LIST><<<grid, block, 0, st>>>(t);
+            knn_tile<P, TILE_LIST, false><<<grid, block, 0, st>>>(t);
         else if (c.death)
-            knn_tile<P, TILE_VIS><<<grid, block, 0, st>>>(t);
+            knn_tile<P, TILE_VIS, false><<<grid, block, 0, st>>>(t);
         else
-            knn_tile<P, TILE_PLAIN><<<grid, block, 0, st>>>(t);
+            knn_tile<P, TILE_PLAIN, false><<<grid, block, 0, st>>>(t);
     } else {
         ATSNE_REQUIRE(!c.death && !b.blk_q, ATSNE_E_UNSUPPORTED, "deletion stamps and tile lists need the FP32 corpus");
-        knn_tile<P, TILE_PLAIN><<<grid, block, 0, st>>>(t);
+        knn_tile<P, TILE_PLAIN, false><<<grid, dim3(TileGeom<P>::THREADS), 0, st>>>(t);
     }
     ATSNE_LAUNCH_CHECK();
     return ATSNE_OK;
@@ -1674,17 +1698,17 @@ static atsne_status make_plan(int64_t N, int64_t M, int32_t D, int prec, int k, 
     // batches of query rows.
     const size_t slot_budget = (size_t)2 << 30;
     const int64_t Mq = std::max<int64_t>(M, 1);
-    SearchPlan full = plan_search(prec, Mq, 0, N, k, kc);
+    SearchPlan full = plan_search(prec, Mq, 0, N, k, kc, 0, true);
     if (full.ws_bytes > slot_budget && full.S > 1) {
         const int64_t s_fit = (int64_t)(slot_budget / ((size_t)Mq * full.cap * 8));
-        full = plan_search(prec, Mq, 0, N, k, kc, (int)std::max<int64_t>(1, std::min<int64_t>(full.S, s_fit)));
+        full = plan_search(prec, Mq, 0, N, k, kc, (int)std::max<int64_t>(1, std::min<int64_t>(full.S, s_fit)), true);
     }
     const int qb = qb_of(prec);
     const size_t per_row = (size_t)full.S * full.cap * 8;
     int64_t max_rows = (int64_t)(slot_budget / per_row);
     max_rows = std::max<int64_t>(qb, max_rows / qb * qb);
     p.Mb = std::min<int64_t>(Mq, max_rows);
-    p.sp = p.Mb < Mq ? plan_search(prec, p.Mb, 0, N, k, kc, full.S) : full;
+    p.sp = p.Mb < Mq ? plan_search(prec, p.Mb, 0, N, k, kc, full.S, true) : full;
     p.total = align_up(p.b_corpus, 256) + p.sp.ws_bytes;
     return ATSNE_OK;
 }
