@@ -826,6 +826,11 @@ extern "C" atsne_status atsne_serve_submit_delete(atsne_server* s, const int32_t
         std::lock_guard<std::mutex> lk(s->mu);
         c = s->commits_submitted;
     }
+    if (c >= (uint64_t)INT_MAX) {  // deletion stamps are int32 commit indices
+        free_request(s, r);
+        set_error("commit index space exhausted");
+        return ATSNE_E_K_RANGE;
+    }
     if (hipMemcpyAsync(s->del_ids, r->ids_host.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice, s->s_copy) !=
             hipSuccess ||
         serve_mark_deleted(s->death, s->del_ids, M, (int32_t)c, s->s_copy) != ATSNE_OK ||
