@@ -11,9 +11,11 @@
 //                  row norms n_i = ||x_i||^2 and the corpus max norm.
 //   knn_tile       S = X_q X_k^T on MFMA, d'_ij = n_j - 2 S_ij (n_i is a row
 //                  constant and irrelevant to the ranking), self and padding
-//                  masked; a running per-(query, split) threshold filters
-//                  candidates into a buffer that a wave-level radix select
-//                  shrinks back to the best k_cand whenever it fills.
+//                  masked; operands staged by direct global -> LDS loads; a
+//                  running per-(query, split) threshold filters candidates
+//                  into a buffer that is cut back (to between k_cand and
+//                  k_cand + slack keys, new threshold) whenever it fills, and
+//                  shrunk exactly to the best k_cand at the end.
 //   knn_select     per query, the best k_cand keys (d', j) over all splits,
 //                  exact FP32 direct-difference distances for them, sorted by
 //                  (d, j); rows whose k-th/(k+1)-th gap is under FP32
@@ -55,7 +57,23 @@ __host__ __device__ constexpr int qb_of(int prec) { return prec == ATSNE_PREC_FP
 constexpr int KT = KNN_KT;      // keys per tile (8 MFMA blocks of 32)
 constexpr int NKB = KT / 32;    // key blocks per tile
 constexpr int CHUNK_UNITS = 8;  // 16-byte units per row per D-chunk (128 bytes)
-constexpr int ROW_UNITS = 9;    // LDS row stride in 16-byte units (one unit of padding)
+
+// LDS tile layout: rows of CHUNK_UNITS unpadded 16-byte units, unit u of row r
+// in slot u ^ lds_swz(r).  For a fixed unit, any 8 consecutive rows, and the
+// 8 even or the 8 odd rows of any 16 consecutive rows aligned to 16, land in
+// distinct 16-byte bank groups, so the MFMA fragment reads (one unit of each
+// of 32 consecutive rows per half-wave) are free of bank conflicts with 32 or
+// with 64 banks.
+__device__ __forceinline__ int lds_swz(int r) { return (r & 7) ^ ((r >> 3) & 1); }
+
+// Direct global -> LDS loads (no register staging): lane i of the wave writes
+// its 16 (or 4) bytes to lds + 16 i (or 4 i); `lds` must be wave-uniform.
+__device__ __forceinline__ void lds_dma16(const uint4* src, uint4* lds) {
+    __builtin_amdgcn_global_load_lds((const void*)src, (__attribute__((address_space(3))) void*)lds, 16, 0, 0);
+}
+__device__ __forceinline__ void lds_dma4(const float* src, float* lds) {
+    __builtin_amdgcn_global_load_lds((const void*)src, (__attribute__((address_space(3))) void*)lds, 4, 0, 0);
+}
 
 // Elements per 128-byte chunk for each precision.
 __host__ __device__ constexpr int chunk_elems(int prec) {
@@ -323,6 +341,133 @@ __device__ Shrunk shrink_slot(uint64_t* slot, int cnt, int kc, uint32_t* hist, c
     return Shrunk{kstar, kc};
 }
 
+// Make room in a candidate slot while streaming: keep every key whose
+// distance code (the order-preserving 32-bit image of the distance) is at
+// most a threshold t chosen so that between kc and kc + allow keys remain,
+// and return t as the slot's new pass threshold.  Any superset of the kc best
+// keys is a valid slot state; the exact cut to kc is left to the final
+// shrink.  The keys are read once into registers; t is searched on the codes
+// between the smallest live code and the largest, each probe one counting
+// pass (ballots and scalar popcounts): regula falsi on the count (Illinois
+// variant), bisection if it has not converged after a few probes.  With deletion stamps (death !=
+// null), keys deleted before the query's view are dropped first.  Slots
+// beyond WAVE * MR_KEYS keys, or ties too wide for the window, take the exact
+// shrink.
+constexpr int MR_KEYS = 12;  // keys per lane held in registers (slots up to 768 keys)
+struct Roomed {
+    float tau;
+    int n;
+};
+// NR registers of keys per lane: the loops are fully unrolled and
+// branch-free (a single instantiation keeps the tile kernel's code small).
+template <int NR>
+__device__ Roomed make_room_nr(uint64_t* slot, int cnt, int kc, int allow, uint32_t* hist, const int32_t* death,
+                               int32_t view) {
+    const int l = lane_id();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    // all loads first, then their uses: one memory latency.  code[i] is the
+    // key's distance code, 0xffffffff for an empty register (above every
+    // live code, and never probed)
+    uint64_t k[NR];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        const int idx = l + WAVE * i;
+        k[i] = idx < cnt ? slot[idx] : ~0ull;
+    }
+    if (death) {
+#pragma unroll
+        for (int i = 0; i < NR; ++i)
+            if (k[i] != ~0ull && death[key_index(k[i])] < view) k[i] = ~0ull;
+    }
+    // a key's distance code is its upper word; an empty register (~0) has
+    // code 0xffffffff, above every distance's code (at most that of +inf)
+    int live = 0;
+    uint32_t lo = 0xffffffffu, hi = 0u;  // smallest / largest live code of this lane
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        const uint32_t code = (uint32_t)(k[i] >> 32);
+        const bool ok = code != 0xffffffffu;
+        live += __popcll(ballot(ok));
+        lo = min(lo, code);
+        hi = max(hi, ok ? code : 0u);
+    }
+    // number of live keys with code <= v (v < 0xffffffff)
+    auto count_le = [&](uint32_t v) {
+        int c = 0;
+#pragma unroll
+        for (int i = 0; i < NR; ++i) c += __popcll(ballot((uint32_t)(k[i] >> 32) <= v));
+        return c;
+    };
+    uint32_t thr = 0xff800000u;  // ordered +inf: keep every live key
+    if (live > kc) {
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            lo = min(lo, (uint32_t)__shfl_xor((int)lo, o, WAVE));
+            hi = max(hi, (uint32_t)__shfl_xor((int)hi, o, WAVE));
+        }
+        // bracket: count_le(a) = ca < kc <= cb = count_le(b); the answer is
+        // in (a, b].  Regula falsi on the count, with the Illinois halving of
+        // a stale end's excess, falling back to bisection after 8 probes.
+        uint32_t a = lo - 1, b = hi;  // (live codes are >= 1)
+        int ca = 0, cb = live;
+        float wa = 1.0f, wb = 1.0f;
+        int side = 0;
+        const float target = (float)kc + 0.5f * (float)allow;
+        bool found = false;
+        for (int it = 0; it < 48; ++it) {
+            if (cb <= kc + allow) {
+                thr = b;
+                found = true;
+                break;
+            }
+            if (b - a <= 1) break;  // more than `allow` keys share code b
+            uint32_t g;
+            if (it < 8) {
+                const float fa = wa * ((float)ca - target), fb = wb * ((float)cb - target);
+                g = a + (uint32_t)((float)(b - a) * (-fa / (fb - fa)));
+            } else {
+                g = a + (b - a) / 2;
+            }
+            g = g <= a ? a + 1 : (g >= b ? b - 1 : g);
+            const int cg = count_le(g);
+            if (cg < kc) {
+                a = g;
+                ca = cg;
+                wb = side == -1 ? 0.5f * wb : 1.0f;
+                wa = 1.0f;
+                side = -1;
+            } else {
+                b = g;
+                cb = cg;
+                wa = side == 1 ? 0.5f * wa : 1.0f;
+                wb = 1.0f;
+                side = 1;
+            }
+        }
+        if (!found) {
+            const Shrunk sh = shrink_slot(slot, cnt, kc, hist, death, view);
+            return Roomed{key_dist(sh.kstar), sh.n};
+        }
+        thr = min(thr, 0xff800000u);
+    }
+    int base = 0;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        const bool keep = (uint32_t)(k[i] >> 32) <= thr;
+        const uint64_t m = ballot(keep);
+        if (keep) slot[base + __popcll(m & lanemask_lt())] = k[i];
+        base += __popcll(m);
+    }
+    // (readers of the slot fence before reading it)
+    return Roomed{live > kc ? ord2f(thr) : INFINITY, base};
+}
+__device__ __noinline__ Roomed make_room(uint64_t* slot, int cnt, int kc, int allow, uint32_t* hist, const int32_t* death,
+                                        int32_t view) {
+    if (cnt <= MR_KEYS * WAVE) return make_room_nr<MR_KEYS>(slot, cnt, kc, allow, hist, death, view);
+    const Shrunk sh = shrink_slot(slot, cnt, kc, hist, death, view);
+    return Roomed{key_dist(sh.kstar), sh.n};
+}
+
 // ---------------------------------------------------------------------------
 // knn_tile: grid = MB query blocks x S key splits.  blockIdx.x -> (split,
 // query block) with the query block fastest, so the workgroups that share an
@@ -384,10 +529,15 @@ __global__ __launch_bounds__((TileGeom<P, SMALL>::THREADS)) __attribute__((amdgp
     constexpr int TILE_WAVES = G::WAVES;
     constexpr int TT = G::THREADS;
     constexpr int RSTEP = TT / 8;  // rows between one thread's staged units
-    // double-buffered tiles: one barrier per chunk, the next chunk's global
-    // loads in flight while this chunk's MFMAs run
-    __shared__ uint4 Ks[2][KT * ROW_UNITS];
-    __shared__ uint4 Qs[2][QB * ROW_UNITS];
+    // double-buffered tiles, filled by direct global -> LDS loads: one barrier
+    // per chunk, the next chunk's loads in flight while this chunk's MFMAs
+    // run.  The two buffers are separate arrays so the compiler can tell the
+    // one being filled from the one being read (it would otherwise wait for
+    // the loads in flight before every fragment read).
+    __shared__ uint4 Ks0[KT * CHUNK_UNITS];
+    __shared__ uint4 Ks1[KT * CHUNK_UNITS];
+    __shared__ uint4 Qs0[QB * CHUNK_UNITS];
+    __shared__ uint4 Qs1[QB * CHUNK_UNITS];
     // per-tile norms/scales: three buffers, because a tile's epilogue runs
     // after the barrier that lets faster waves stage the following tiles
     __shared__ float Kn[3][KT];
@@ -396,7 +546,7 @@ __global__ __launch_bounds__((TileGeom<P, SMALL>::THREADS)) __attribute__((amdgp
 
     const int t = threadIdx.x;
     const int l = t & 63;
-    const int w = t >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6);  // wave-uniform: LDS bases go to M0
     constexpr bool VIS = MODE == TILE_VIS;
     constexpr bool LIST = MODE == TILE_LIST;
     // XCD-aware order: workgroup b is dispatched to XCD b % 8, and each XCD
@@ -435,23 +585,29 @@ __global__ __launch_bounds__((TileGeom<P, SMALL>::THREADS)) __attribute__((amdgp
     const int64_t row_units = a.row_units;
     const int n_chunks = a.n_chunks;
 
-    // Rows of the query tile this thread loads (4 rows, unit t & 7).
+    // Staging map: load instruction j of wave w fills rows 8 (w + WAVES j) ..
+    // + 7 of a tile (1 KiB of LDS), lane l row (t >> 3) + RSTEP j and slot
+    // l & 7, which holds global unit ulane (the swizzle of that row; WAVES is
+    // even, so the row's bit 3 is w & 1).
+    static_assert(TILE_WAVES % 2 == 0 && RSTEP == 8 * TILE_WAVES, "staging map");
+    const int ulane = (l & 7) ^ (l >> 3) ^ (w & 1);
+    // Corpus rows of the 4 query-tile rows this lane loads (kept as 32-bit
+    // row numbers; the 64-bit unit offsets are formed per chunk).
     auto qrow_of = [&](int i) {
         const int64_t m = qbase + (t >> 3) + RSTEP * i;
-        const int64_t row = m < qend ? load_qid(a.qids, a.m0, m) : 0;
-        return row * row_units + (t & 7);
+        return (uint32_t)(m < qend ? load_qid(a.qids, a.m0, m) : 0);
     };
-    const int64_t qoff0 = qrow_of(0), qoff1 = qrow_of(1), qoff2 = qrow_of(2), qoff3 = qrow_of(3);
+    const uint32_t qr0 = qrow_of(0), qr1 = qrow_of(1), qr2 = qrow_of(2), qr3 = qrow_of(3);
 
     // Per-lane query state (lanes l and l+32 share query 32w + l%32).
     const int qloc = 32 * w + (l & 31);
     const int64_t mq = qbase + qloc;
     const bool qvalid = mq < qend;
-    const int64_t self = qvalid ? load_qid(a.qids, a.m0, mq) : -1;
-    const int64_t nl = qvalid ? (a.nlims ? (int64_t)a.nlims[mq] : a.nlim) : 0;
+    // corpus rows and keys are int32 (row counts are checked on the host)
+    const int32_t self = qvalid ? (int32_t)load_qid(a.qids, a.m0, mq) : -1;
+    const int32_t nl = qvalid ? (int32_t)(a.nlims ? (int64_t)a.nlims[mq] : a.nlim) : 0;
     const int kcq = qvalid ? (a.kcs ? a.kcs[mq] : a.kc) : 0;
     const int sq_e8 = (P == ATSNE_PREC_FP8_E4M3 && qvalid) ? e8m0_of(a.scales[self]) : 127;
-    uint64_t* myslot = a.slots + ((size_t)(qvalid ? mq : 0) * a.S + split) * (size_t)a.cap;
     float tau = -INFINITY;
     const int32_t* death = VIS ? a.death : nullptr;
     if (qvalid && key_visible(death, self, a.views ? a.views[mq] : a.view)) {
@@ -467,78 +623,55 @@ __global__ __launch_bounds__((TileGeom<P, SMALL>::THREADS)) __attribute__((amdgp
         }
     }
     // smallest key bound of the wave's queries: tiles below it need no range checks
-    int nl_min = qvalid ? (int)nl : 0x7fffffff;
+    int nl_min = qvalid ? nl : 0x7fffffff;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) nl_min = min(nl_min, __shfl_xor(nl_min, o, WAVE));
     int count = 0;
 
-    // Global -> register staging of one chunk (8 key units + 4 query units per
-    // thread) and register -> LDS parking.  Written as macros over plain
-    // locals so the staging stays in registers.
-    // Global -> register staging of one chunk (4 key units + 4 query units
-    // per thread, rows 64 apart) and register -> LDS parking.  Written as
-    // macros over named locals so the staging stays in registers.
-    uint4 pk0, pk1, pk2, pk3, pk4, pk5, pk6, pk7, pq0, pq1, pq2, pq3;
-    const int64_t krow_ = (int64_t)(t >> 3) * row_units + (t & 7);
+    // Direct global -> LDS staging of one chunk into buffer PB: KT / RSTEP key
+    // rows and 4 query rows per lane, and at a tile's first chunk the tile's
+    // norms (and FP8 scales), one dword per lane of the first KT / 64 waves.
+    const uint32_t krow_ = (uint32_t)((t >> 3) * row_units) + ulane;  // < KT row_units
     const int64_t kstep_ = RSTEP * row_units;
-#define ATSNE_LOAD_CHUNK(TILE, C)                                                                    \
-    do {                                                                                             \
-        const uint4* kb_ = a.Xp + (int64_t)(TILE) * KT * row_units + (int64_t)(C) * CHUNK_UNITS + krow_; \
-        pk0 = kb_[0];                                                                                \
-        pk1 = kb_[kstep_];                                                                           \
-        pk2 = kb_[2 * kstep_];                                                                       \
-        pk3 = kb_[3 * kstep_];                                                                       \
-        if (KT / RSTEP == 8) {                                                                       \
-            pk4 = kb_[4 * kstep_];                                                                   \
-            pk5 = kb_[5 * kstep_];                                                                   \
-            pk6 = kb_[6 * kstep_];                                                                   \
-            pk7 = kb_[7 * kstep_];                                                                   \
-        }                                                                                            \
-        const int64_t co_ = (int64_t)(C) * CHUNK_UNITS;                                              \
-        pq0 = a.Xp[qoff0 + co_];                                                                     \
-        pq1 = a.Xp[qoff1 + co_];                                                                     \
-        pq2 = a.Xp[qoff2 + co_];                                                                     \
-        pq3 = a.Xp[qoff3 + co_];                                                                     \
-    } while (0)
-#define ATSNE_STORE_CHUNK(BUF, POS, TILE, C)                                                         \
-    do {                                                                                             \
-        uint4* ks_ = &Ks[BUF][(t >> 3) * ROW_UNITS + (t & 7)];                                      \
-        ks_[0] = pk0;                                                                                \
-        ks_[RSTEP * ROW_UNITS] = pk1;                                                                \
-        ks_[2 * RSTEP * ROW_UNITS] = pk2;                                                            \
-        ks_[3 * RSTEP * ROW_UNITS] = pk3;                                                            \
-        if (KT / RSTEP == 8) {                                                                       \
-            ks_[4 * RSTEP * ROW_UNITS] = pk4;                                                        \
-            ks_[5 * RSTEP * ROW_UNITS] = pk5;                                                        \
-            ks_[6 * RSTEP * ROW_UNITS] = pk6;                                                        \
-            ks_[7 * RSTEP * ROW_UNITS] = pk7;                                                        \
-        }                                                                                            \
-        uint4* qs_ = &Qs[BUF][(t >> 3) * ROW_UNITS + (t & 7)];                                      \
-        qs_[0] = pq0;                                                                                \
-        qs_[RSTEP * ROW_UNITS] = pq1;                                                                \
-        qs_[2 * RSTEP * ROW_UNITS] = pq2;                                                            \
-        qs_[3 * RSTEP * ROW_UNITS] = pq3;                                                            \
-        if ((C) == 0 && t < KT) {                                                                    \
-            Kn[(POS) % 3][t] = a.norms[(int64_t)(TILE) * KT + t];                                   \
-            if constexpr (P == ATSNE_PREC_FP8_E4M3) Ksc[(POS) % 3][t] = a.scales[(int64_t)(TILE) * KT + t]; \
-        }                                                                                            \
-    } while (0)
+    auto issue = [&](auto par_tag, int pos, int c) __attribute__((always_inline)) {
+        constexpr bool PB = decltype(par_tag)::value;
+        uint4* ks = PB ? Ks1 : Ks0;
+        uint4* qs = PB ? Qs1 : Qs0;
+        const int64_t tile_row = (int64_t)tile_id(pos) * KT;
+        const int64_t co = (int64_t)c * CHUNK_UNITS;
+        const uint4* kb = a.Xp + tile_row * row_units + co + krow_;
+#pragma unroll
+        for (int j = 0; j < KT / RSTEP; ++j) lds_dma16(kb + j * kstep_, ks + 64 * (w + TILE_WAVES * j));
+        const uint4* qb = a.Xp + co + ulane;
+        lds_dma16(qb + (uint64_t)qr0 * (uint64_t)row_units, qs + 64 * w);
+        lds_dma16(qb + (uint64_t)qr1 * (uint64_t)row_units, qs + 64 * (w + TILE_WAVES));
+        lds_dma16(qb + (uint64_t)qr2 * (uint64_t)row_units, qs + 64 * (w + 2 * TILE_WAVES));
+        lds_dma16(qb + (uint64_t)qr3 * (uint64_t)row_units, qs + 64 * (w + 3 * TILE_WAVES));
+        if (c == 0 && w < KT / 64) {
+            lds_dma4(a.norms + tile_row + 64 * w + l, &Kn[pos % 3][64 * w]);
+            if constexpr (P == ATSNE_PREC_FP8_E4M3) lds_dma4(a.scales + tile_row + 64 * w + l, &Ksc[pos % 3][64 * w]);
+        }
+    };
+    // fragment slot of this lane's rows (32 b + l % 32 and 32 w + l % 32)
+    const int sw = lds_swz(l & 31);
 
     f32x16 acc[NKB];
     int ksc_e8[NKB];
-    // One chunk of the contraction from LDS buffer `buf`: key blocks in pairs,
+    // One chunk of the contraction from LDS buffer PB: key blocks in pairs,
     // the next pair's fragments read while the current pair's MFMAs run.
-    auto compute = [&](int buf, auto first_tag) __attribute__((always_inline)) {
-        constexpr bool FIRST = decltype(first_tag)::value;
-        const uint4* K = Ks[buf];
+    auto compute = [&](auto par_tag) __attribute__((always_inline)) {
+        constexpr bool PB = decltype(par_tag)::value;
+        constexpr bool FIRST = false;  // accumulators are cleared at each tile's start
+        const uint4* K = PB ? Ks1 : Ks0;
+        const uint4* Q = PB ? Qs1 : Qs0;
         uint4 bq[4], ca0[4], ca1[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) bq[i] = Qs[buf][qloc * ROW_UNITS + chunk_unit<P>(l, i)];
+        for (int i = 0; i < 4; ++i) bq[i] = Q[qloc * CHUNK_UNITS + (chunk_unit<P>(l, i) ^ sw)];
         if constexpr (P == ATSNE_PREC_FP8_E4M3) {
 #pragma unroll
             for (int b = 0; b < NKB; ++b) {
 #pragma unroll
-                for (int i = 0; i < 4; ++i) ca0[i] = K[(32 * b + (l & 31)) * ROW_UNITS + chunk_unit<P>(l, i)];
+                for (int i = 0; i < 4; ++i) ca0[i] = K[(32 * b + (l & 31)) * CHUNK_UNITS + (chunk_unit<P>(l, i) ^ sw)];
                 mfma_fp8_block<FIRST>(acc[b], ca0, bq, ksc_e8[b], sq_e8);
                 // keep the next block's operand reads from being hoisted over
                 // these MFMAs (register budget at two waves per SIMD)
@@ -549,8 +682,8 @@ __global__ __launch_bounds__((TileGeom<P, SMALL>::THREADS)) __attribute__((amdgp
             for (int pr = 0; pr < NKB / 2; ++pr) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    ca0[i] = K[(64 * pr + (l & 31)) * ROW_UNITS + chunk_unit<P>(l, i)];
-                    ca1[i] = K[(64 * pr + 32 + (l & 31)) * ROW_UNITS + chunk_unit<P>(l, i)];
+                    ca0[i] = K[(64 * pr + (l & 31)) * CHUNK_UNITS + (chunk_unit<P>(l, i) ^ sw)];
+                    ca1[i] = K[(64 * pr + 32 + (l & 31)) * CHUNK_UNITS + (chunk_unit<P>(l, i) ^ sw)];
                 }
                 mfma_pair<P, FIRST>(acc[2 * pr], acc[2 * pr + 1], ca0, ca1, bq, 127, 127, 127);
             }
@@ -558,62 +691,69 @@ __global__ __launch_bounds__((TileGeom<P, SMALL>::THREADS)) __attribute__((amdgp
     };
 
     auto epilogue = [&](int pos) __attribute__((always_inline)) {
-        // make room, then filter this tile's candidates
-        {
-            uint64_t need = ballot(count > a.cap - KT) & 0xffffffffull;
-            while (need) {
-                int q = __ffsll((unsigned long long)need) - 1;
-                need &= need - 1;
-                int cnt_q = __shfl(count, q, WAVE);
-                int kc_q = __shfl(kcq, q, WAVE);
-                uint64_t* sq = a.slots + ((size_t)(qbase + 32 * w + q) * a.S + split) * (size_t)a.cap;
-                const int32_t v_q = a.views ? a.views[qbase + 32 * w + q] : a.view;
-                const Shrunk sh = shrink_slot(sq, cnt_q, kc_q, hist, death, v_q);
-                if ((l & 31) == q) {
-                    count = sh.n;
-                    tau = fminf(tau, key_dist(sh.kstar));
-                }
-            }
-        }
         const int key0 = tile_id(pos) * KT;
-        // tiles inside every query's key range skip the per-key range checks
+        // tiles inside every query's key range, and not holding the query
+        // itself, skip the per-key checks
         const bool edge = key0 < a.key_lo || key0 + KT > nl_min;
+        const bool has_self = ballot(self >= key0 && self < key0 + KT) != 0;
         const float* kn = Kn[pos % 3];
+        // A lane holds 16 values of each key block for its query; lane l and
+        // l + 32 share query l % 32 and append their passing keys to its slot
+        // side by side (lane l first), so no wave-wide compaction is needed.
 #pragma unroll
         for (int b = 0; b < NKB; ++b) {
-            // block-level test first: one compare and one branch for the 16
-            // candidates a lane holds in this key block (almost always none
-            // passes once the threshold has settled)
-            float dmin = INFINITY;
+            float dv[16];
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
                 const float4 nj = *reinterpret_cast<const float4*>(&kn[32 * b + 8 * g + 4 * (l >> 5)]);
-                dmin = fminf(dmin, fminf(fminf(fmaf(-2.0f, acc[b][4 * g + 0], nj.x), fmaf(-2.0f, acc[b][4 * g + 1], nj.y)),
-                                         fminf(fmaf(-2.0f, acc[b][4 * g + 2], nj.z), fmaf(-2.0f, acc[b][4 * g + 3], nj.w))));
+                dv[4 * g + 0] = fmaf(-2.0f, acc[b][4 * g + 0], nj.x);
+                dv[4 * g + 1] = fmaf(-2.0f, acc[b][4 * g + 1], nj.y);
+                dv[4 * g + 2] = fmaf(-2.0f, acc[b][4 * g + 2], nj.z);
+                dv[4 * g + 3] = fmaf(-2.0f, acc[b][4 * g + 3], nj.w);
             }
+            // block-level test first: almost always nothing passes once the
+            // threshold has settled
+            float dmin = dv[0];
+#pragma unroll
+            for (int v = 1; v < 16; ++v) dmin = fminf(dmin, dv[v]);
             if (!ballot(dmin < tau)) continue;
+            const int kb = key0 + 32 * b + 4 * (l >> 5);  // key of value v: kb + 8 (v / 4) + v % 4
+            uint32_t mask = 0;
 #pragma unroll
-            for (int g = 0; g < 4; ++g) {
-                const int kl = 32 * b + 8 * g + 4 * (l >> 5);
-                const float4 nj = *reinterpret_cast<const float4*>(&kn[kl]);
+            for (int v = 0; v < 16; ++v) mask |= (dv[v] < tau ? 1u : 0u) << v;
+            if (edge || has_self) {
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const float nje = e == 0 ? nj.x : e == 1 ? nj.y : e == 2 ? nj.z : nj.w;
-                    const float d = fmaf(-2.0f, acc[b][4 * g + e], nje);
-                    const int key = key0 + kl + e;
-                    bool pass = d < tau;
-                    if (edge) pass = pass && key >= a.key_lo && key < nl;
-                    if (ballot(pass)) {
-                        pass = pass && key != self;
-                        const uint64_t m = ballot(pass);
-                        const uint32_t lo = (uint32_t)m, hi = (uint32_t)(m >> 32);
-                        const int q = l & 31;
-                        const int bl = (lo >> q) & 1, bh = (hi >> q) & 1;
-                        const int pos = count + ((l >> 5) ? bl : 0);
-                        if (pass) myslot[pos] = pack_key(d, key);
-                        count += bl + bh;
-                    }
+                for (int v = 0; v < 16; ++v) {
+                    const int key = kb + 8 * (v >> 2) + (v & 3);
+                    if (key < a.key_lo || key >= nl || key == self) mask &= ~(1u << v);
                 }
+            }
+            const int n_me = __popc(mask);
+            const int n_other = __shfl_xor(n_me, 32, WAVE);
+            if (n_me) {
+                // the slot pointer is formed here, not held across the chunk loop
+                uint64_t* dst = a.slots + ((size_t)mq * a.S + split) * (size_t)a.cap + count + ((l >> 5) ? n_other : 0);
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    if (mask & (1u << v)) *dst++ = pack_key(dv[v], kb + 8 * (v >> 2) + (v & 3));
+                }
+            }
+            count += n_me + n_other;
+        }
+        // make room for the next tile (the accumulators are dead here, so the
+        // shrink has the registers to itself)
+        uint64_t need = ballot(count > a.cap - KT) & 0xffffffffull;
+        while (need) {
+            const int q = __ffsll((unsigned long long)need) - 1;
+            need &= need - 1;
+            const int cnt_q = __shfl(count, q, WAVE);
+            const int kc_q = __shfl(kcq, q, WAVE);
+            uint64_t* sq = a.slots + ((size_t)(qbase + 32 * w + q) * a.S + split) * (size_t)a.cap;
+            const int32_t v_q = a.views ? a.views[qbase + 32 * w + q] : a.view;
+            const Roomed r = make_room(sq, cnt_q, kc_q, (a.cap - KT - kc_q) / 4, hist, death, v_q);
+            if ((l & 31) == q) {
+                count = r.n;
+                tau = fminf(tau, r.tau);
             }
         }
     };
@@ -621,13 +761,25 @@ __global__ __launch_bounds__((TileGeom<P, SMALL>::THREADS)) __attribute__((amdgp
     const int n_tiles = max(0, tile_end - tile_begin);
     const int total_g = n_tiles * n_chunks;
     if (total_g > 0) {
-        ATSNE_LOAD_CHUNK(tile_id(tile_begin), 0);
-        ATSNE_STORE_CHUNK(0, tile_begin, tile_id(tile_begin), 0);
-        if (total_g > 1) ATSNE_LOAD_CHUNK(tile_id(tile_begin + (n_chunks > 1 ? 0 : 1)), n_chunks > 1 ? 1 : 0);
+        issue(std::false_type{}, tile_begin, 0);
         __syncthreads();
     }
+    // One chunk from buffer PB: start the loads of the next chunk into the
+    // other buffer (read by every wave before the previous barrier), run this
+    // chunk's MFMAs, then one barrier, which also waits for those loads.
     int g = 0;
-    for (int tile = tile_begin; tile < tile_end; ++tile) {
+    auto step = [&](auto par_tag, int tile, int c) __attribute__((always_inline)) {
+        constexpr bool PB = decltype(par_tag)::value;
+        if (g + 1 < total_g) {
+            const bool last = c + 1 == n_chunks;
+            issue(std::integral_constant<bool, !PB>{}, last ? tile + 1 : tile, last ? 0 : c + 1);
+        }
+        compute(par_tag);
+        ++g;
+        __syncthreads();
+    };
+    // per-tile setup: clear the accumulators, fetch the FP8 key scales
+    auto tile_start = [&](int tile) __attribute__((always_inline)) {
         if constexpr (P == ATSNE_PREC_FP8_E4M3) {
 #pragma unroll
             for (int b = 0; b < NKB; ++b) ksc_e8[b] = e8m0_of(Ksc[tile % 3][32 * b + (l & 31)]);
@@ -635,25 +787,28 @@ __global__ __launch_bounds__((TileGeom<P, SMALL>::THREADS)) __attribute__((amdgp
 #pragma unroll
             for (int b = 0; b < NKB; ++b) ksc_e8[b] = 127;
         }
-        for (int c = 0; c < n_chunks; ++c, ++g) {
-            if (c == 0)
-                compute(g & 1, std::true_type{});
-            else
-                compute(g & 1, std::false_type{});
-            if (g + 1 < total_g) {
-                // regs hold chunk g+1; park it in the other buffer, fetch g+2
-                const int c1 = (c + 1 == n_chunks) ? 0 : c + 1;
-                const int t1 = (c + 1 == n_chunks) ? tile + 1 : tile;
-                ATSNE_STORE_CHUNK((g + 1) & 1, t1, tile_id(t1), c1);
-                if (g + 2 < total_g) {
-                    const int c2 = (c1 + 1 == n_chunks) ? 0 : c1 + 1;
-                    const int t2 = (c1 + 1 == n_chunks) ? t1 + 1 : t1;
-                    ATSNE_LOAD_CHUNK(tile_id(t2), c2);
-                }
-            }
-            __syncthreads();
+#pragma unroll
+        for (int b = 0; b < NKB; ++b) acc[b] = f32x16{};
+    };
+    // The chunk sequence runs across tiles with the buffers alternating, two
+    // chunks per iteration so each step's buffer is fixed at compile time
+    // (a runtime choice between two instantiations makes the register
+    // allocator copy the accumulators).
+    int tile = tile_begin, c = 0;
+    auto advance = [&]() __attribute__((always_inline)) {
+        if (++c == n_chunks) {
+            epilogue(tile);
+            c = 0;
+            if (++tile < tile_end) tile_start(tile);
         }
-        epilogue(tile);
+    };
+    if (total_g > 0) tile_start(tile);
+    while (g < total_g) {
+        step(std::false_type{}, tile, c);
+        advance();
+        if (g == total_g) break;
+        step(std::true_type{}, tile, c);
+        advance();
     }
 
     // Final shrink so each slot hands at most max(kc, final_keep) candidates
@@ -672,8 +827,6 @@ __global__ __launch_bounds__((TileGeom<P, SMALL>::THREADS)) __attribute__((amdgp
         }
     }
     if (qvalid && l < 32) a.counts[mq * a.S + split] = count;
-#undef ATSNE_LOAD_CHUNK
-#undef ATSNE_STORE_CHUNK
 }
 
 // ---------------------------------------------------------------------------
