@@ -468,6 +468,42 @@ __device__ __noinline__ Roomed make_room(uint64_t* slot, int cnt, int kc, int al
     return Roomed{key_dist(sh.kstar), sh.n};
 }
 
+// Balanced schedule: workgroup p of P covers units [floor(p W / P),
+// floor((p + 1) W / P)) of the W = MB T (query block, key tile) units.
+// owner(u) is the workgroup covering unit u; stream_segments lists the
+// (query block, split, first tile, end tile) segments of workgroup p (at
+// most max_seg; returns their number).  Host and device use this same code.
+constexpr int STREAM_MAX_SEG = 32;
+__host__ __device__ inline int stream_owner(int64_t u, int64_t W, int P) {
+    int p = (int)((u * P) / W);
+    while (p + 1 < P && ((int64_t)(p + 1) * W) / P <= u) ++p;
+    while (p > 0 && ((int64_t)p * W) / P > u) --p;
+    return p;
+}
+__host__ __device__ inline int stream_segments(int p, int MB, int T, int P, int4* out, int max_seg) {
+    const int64_t W = (int64_t)MB * T;
+    int64_t u = ((int64_t)p * W) / P;
+    const int64_t u1 = ((int64_t)(p + 1) * W) / P;
+    int n = 0;
+    while (u < u1 && n < max_seg) {
+        const int qb = (int)(u / T);
+        const int tb = (int)(u - (int64_t)qb * T);
+        const int te = (int)((u1 - u < (int64_t)(T - tb)) ? tb + (u1 - u) : T);
+        out[n++] = make_int4(qb, p - stream_owner((int64_t)qb * T, W, P), tb, te);
+        u += te - tb;
+    }
+    return u < u1 ? -1 : n;
+}
+
+// One thread per workgroup of the balanced schedule writes its segment list.
+__global__ void knn_stream_segments(int MB, int T, int P, int4* __restrict__ segs) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    int4* o = segs + (size_t)p * (STREAM_MAX_SEG + 1);
+    const int n = stream_segments(p, MB, T, P, o, STREAM_MAX_SEG);
+    o[n < 0 ? 0 : n] = make_int4(-1, 0, 0, 0);
+}
+
 // ---------------------------------------------------------------------------
 // knn_tile: grid = MB query blocks x S key splits.  blockIdx.x -> (split,
 // query block) with the query block fastest, so the workgroups that share an
@@ -495,6 +531,12 @@ struct TileArgs {
     const int32_t* views;
     int32_t view;
     int MB, S, tiles_per_split, tile_lo, tile_hi, cap;
+    // balanced schedule (segs != null): one workgroup per resident slot, each
+    // taking an equal contiguous range of the MB x (tile_hi - tile_lo)
+    // (query block, key tile) units; segs[p] lists workgroup p's segments as
+    // (query block, split, first tile, end tile) with split = the index of
+    // the workgroup among those covering the query block, -1 after the last
+    const int4* segs;
     // the final shrink runs for slots above max(kc, final_keep): a split of a
     // single tile hands all its keys to the select, whose union threshold is
     // one parallel pass per row instead of a serial shrink per query here
@@ -549,31 +591,13 @@ __global__ __launch_bounds__((TileGeom<P, SMALL>::THREADS)) __attribute__((amdgp
     const int w = __builtin_amdgcn_readfirstlane(t >> 6);  // wave-uniform: LDS bases go to M0
     constexpr bool VIS = MODE == TILE_VIS;
     constexpr bool LIST = MODE == TILE_LIST;
-    // XCD-aware order: workgroup b is dispatched to XCD b % 8, and each XCD
-    // gets a contiguous run of (query block, split) tasks with the split
-    // fastest, so the workgroups resident on one XCD share a few query blocks
-    // and the same key tiles through its L2.
-    const int n_tasks = a.MB * a.S;
+    // XCD-aware order: workgroup b is dispatched to XCD b % 8.  Task grid:
+    // each XCD gets a contiguous run of (query block, split) tasks with the
+    // split fastest, so the workgroups resident on one XCD share a few query
+    // blocks and the same key tiles through its L2.  Balanced schedule: each
+    // XCD gets a contiguous eighth of the units.
     const int xcd = (int)(blockIdx.x % KNN_XCDS), jx = (int)(blockIdx.x / KNN_XCDS);
-    const int task = xcd * (n_tasks / KNN_XCDS) + min(xcd, n_tasks % KNN_XCDS) + jx;
-    const int qb = task / a.S;
-    const int split = task % a.S;
-    // this block's query rows and this split's positions in its tile sequence
-    int64_t qbase, qend;
-    int tile_begin, tile_end;
-    if constexpr (LIST) {
-        qbase = a.blk_q[qb];
-        qend = a.blk_q[qb + 1];
-        const int l0 = a.blk_t[qb], l1 = a.blk_t[qb + 1];
-        const int tps = (l1 - l0 + a.S - 1) / a.S;
-        tile_begin = min(l1, l0 + split * tps);
-        tile_end = min(l1, tile_begin + tps);
-    } else {
-        qbase = (int64_t)qb * QB;
-        qend = a.M;
-        tile_begin = a.tile_lo + split * a.tiles_per_split;
-        tile_end = min(a.tile_hi, tile_begin + a.tiles_per_split);
-    }
+    const int4* my_segs = a.segs ? a.segs + (size_t)(xcd * ((int)gridDim.x / KNN_XCDS) + jx) * (STREAM_MAX_SEG + 1) : nullptr;
     // corpus tile at sequence position p
     auto tile_id = [&](int p) __attribute__((always_inline)) {
         if constexpr (LIST)
@@ -584,6 +608,50 @@ __global__ __launch_bounds__((TileGeom<P, SMALL>::THREADS)) __attribute__((amdgp
     uint32_t* hist = hist_all[w];
     const int64_t row_units = a.row_units;
     const int n_chunks = a.n_chunks;
+    // A workgroup runs one segment (query block, split, tile range), or in the
+    // balanced schedule the up to three segments its unit range crosses.
+    // A workgroup runs one segment (query block, split, tile range), or in the
+    // balanced schedule the segments its unit range crosses, one after the
+    // other inside the single chunk loop below.
+    int seg = 0;
+    int qb = 0, split = 0;
+    int64_t qbase = 0, qend = 0;
+    int tile_begin = 0, tile_end = 0;
+    bool qb_done = false;  // this segment ends its query block (balanced schedule)
+    auto load_segment = [&](int sidx) __attribute__((always_inline)) {
+        if (my_segs) {
+            const int4 sg = my_segs[sidx];
+            if (sg.x < 0) return false;
+            qb = sg.x;
+            split = sg.y;
+            qbase = (int64_t)qb * QB;
+            qend = a.M;
+            tile_begin = a.tile_lo + sg.z;
+            tile_end = a.tile_lo + sg.w;
+            qb_done = sg.w == a.tile_hi - a.tile_lo;
+            return true;
+        }
+        if (sidx > 0) return false;
+        const int n_tasks = a.MB * a.S;
+        const int task = xcd * (n_tasks / KNN_XCDS) + min(xcd, n_tasks % KNN_XCDS) + jx;
+        qb = task / a.S;
+        split = task % a.S;
+        // this block's query rows and this split's positions in its tile sequence
+        if constexpr (LIST) {
+            qbase = a.blk_q[qb];
+            qend = a.blk_q[qb + 1];
+            const int l0 = a.blk_t[qb], l1 = a.blk_t[qb + 1];
+            const int tps = (l1 - l0 + a.S - 1) / a.S;
+            tile_begin = min(l1, l0 + split * tps);
+            tile_end = min(l1, tile_begin + tps);
+        } else {
+            qbase = (int64_t)qb * QB;
+            qend = a.M;
+            tile_begin = a.tile_lo + split * a.tiles_per_split;
+            tile_end = min(a.tile_hi, tile_begin + a.tiles_per_split);
+        }
+        return true;
+    };
 
     // Staging map: load instruction j of wave w fills rows 8 (w + WAVES j) ..
     // + 7 of a tile (1 KiB of LDS), lane l row (t >> 3) + RSTEP j and slot
@@ -591,42 +659,52 @@ __global__ __launch_bounds__((TileGeom<P, SMALL>::THREADS)) __attribute__((amdgp
     // even, so the row's bit 3 is w & 1).
     static_assert(TILE_WAVES % 2 == 0 && RSTEP == 8 * TILE_WAVES, "staging map");
     const int ulane = (l & 7) ^ (l >> 3) ^ (w & 1);
-    // Corpus rows of the 4 query-tile rows this lane loads (kept as 32-bit
-    // row numbers; the 64-bit unit offsets are formed per chunk).
-    auto qrow_of = [&](int i) {
-        const int64_t m = qbase + (t >> 3) + RSTEP * i;
-        return (uint32_t)(m < qend ? load_qid(a.qids, a.m0, m) : 0);
-    };
-    const uint32_t qr0 = qrow_of(0), qr1 = qrow_of(1), qr2 = qrow_of(2), qr3 = qrow_of(3);
-
-    // Per-lane query state (lanes l and l+32 share query 32w + l%32).
+    // Per-segment query state.  Corpus rows of the 4 query-tile rows this
+    // lane loads (kept as 32-bit row numbers; the 64-bit unit offsets are
+    // formed per chunk); lanes l and l+32 share query 32w + l%32.
     const int qloc = 32 * w + (l & 31);
-    const int64_t mq = qbase + qloc;
-    const bool qvalid = mq < qend;
-    // corpus rows and keys are int32 (row counts are checked on the host)
-    const int32_t self = qvalid ? (int32_t)load_qid(a.qids, a.m0, mq) : -1;
-    const int32_t nl = qvalid ? (int32_t)(a.nlims ? (int64_t)a.nlims[mq] : a.nlim) : 0;
-    const int kcq = qvalid ? (a.kcs ? a.kcs[mq] : a.kc) : 0;
-    const int sq_e8 = (P == ATSNE_PREC_FP8_E4M3 && qvalid) ? e8m0_of(a.scales[self]) : 127;
-    float tau = -INFINITY;
     const int32_t* death = VIS ? a.death : nullptr;
-    if (qvalid && key_visible(death, self, a.views ? a.views[mq] : a.view)) {
-        tau = INFINITY;
-        if (a.tau0) {
-            // reverse mode: only keys that may beat the row's farthest
-            // neighbour; d' = d - n_q, widened by the contraction bound
-            const float nq = a.norms[self];
-            const float nmax = nl > 0 ? a.pmax[nl - 1] : 0.0f;
-            const float dmax = a.tau0[mq * a.tau0_stride];
-            tau = dmax > -INFINITY ? dmax - nq + fp32_contraction_bound(a.Dp, nq, nmax, dmax) * 2.0f + 1e-30f
-                                   : -INFINITY;  // a row with no neighbour left takes none
+    uint32_t qr0 = 0, qr1 = 0, qr2 = 0, qr3 = 0;
+    int64_t mq = 0;
+    bool qvalid = false;
+    // corpus rows and keys are int32 (row counts are checked on the host)
+    int32_t self = -1, nl = 0;
+    int kcq = 0, sq_e8 = 127, nl_min = 0, count = 0;
+    float tau = -INFINITY;
+    auto init_query = [&]() __attribute__((always_inline)) {
+        auto qrow_of = [&](int i) {
+            const int64_t m = qbase + (t >> 3) + RSTEP * i;
+            return (uint32_t)(m < qend ? load_qid(a.qids, a.m0, m) : 0);
+        };
+        qr0 = qrow_of(0);
+        qr1 = qrow_of(1);
+        qr2 = qrow_of(2);
+        qr3 = qrow_of(3);
+        mq = qbase + qloc;
+        qvalid = mq < qend;
+        self = qvalid ? (int32_t)load_qid(a.qids, a.m0, mq) : -1;
+        nl = qvalid ? (int32_t)(a.nlims ? (int64_t)a.nlims[mq] : a.nlim) : 0;
+        kcq = qvalid ? (a.kcs ? a.kcs[mq] : a.kc) : 0;
+        sq_e8 = (P == ATSNE_PREC_FP8_E4M3 && qvalid) ? e8m0_of(a.scales[self]) : 127;
+        tau = -INFINITY;
+        if (qvalid && key_visible(death, self, a.views ? a.views[mq] : a.view)) {
+            tau = INFINITY;
+            if (a.tau0) {
+                // reverse mode: only keys that may beat the row's farthest
+                // neighbour; d' = d - n_q, widened by the contraction bound
+                const float nq = a.norms[self];
+                const float nmax = nl > 0 ? a.pmax[nl - 1] : 0.0f;
+                const float dmax = a.tau0[mq * a.tau0_stride];
+                tau = dmax > -INFINITY ? dmax - nq + fp32_contraction_bound(a.Dp, nq, nmax, dmax) * 2.0f + 1e-30f
+                                       : -INFINITY;  // a row with no neighbour left takes none
+            }
         }
-    }
-    // smallest key bound of the wave's queries: tiles below it need no range checks
-    int nl_min = qvalid ? nl : 0x7fffffff;
+        // smallest key bound of the wave's queries: tiles below it need no range checks
+        nl_min = qvalid ? nl : 0x7fffffff;
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) nl_min = min(nl_min, __shfl_xor(nl_min, o, WAVE));
-    int count = 0;
+        for (int o = 32; o >= 1; o >>= 1) nl_min = min(nl_min, __shfl_xor(nl_min, o, WAVE));
+        count = 0;
+    };
 
     // Direct global -> LDS staging of one chunk into buffer PB: KT / RSTEP key
     // rows and 4 query rows per lane, and at a tile's first chunk the tile's
@@ -758,25 +836,27 @@ __global__ __launch_bounds__((TileGeom<P, SMALL>::THREADS)) __attribute__((amdgp
         }
     };
 
-    const int n_tiles = max(0, tile_end - tile_begin);
-    const int total_g = n_tiles * n_chunks;
-    if (total_g > 0) {
-        issue(std::false_type{}, tile_begin, 0);
-        __syncthreads();
-    }
-    // One chunk from buffer PB: start the loads of the next chunk into the
-    // other buffer (read by every wave before the previous barrier), run this
-    // chunk's MFMAs, then one barrier, which also waits for those loads.
-    int g = 0;
-    auto step = [&](auto par_tag, int tile, int c) __attribute__((always_inline)) {
-        constexpr bool PB = decltype(par_tag)::value;
-        if (g + 1 < total_g) {
-            const bool last = c + 1 == n_chunks;
-            issue(std::integral_constant<bool, !PB>{}, last ? tile + 1 : tile, last ? 0 : c + 1);
+    // Final shrink so each slot hands at most max(kc, final_keep) candidates
+    // to the next stage; then the slot's count (and, in the balanced
+    // schedule, the query block's last workgroup clears the splits nobody
+    // covers).
+    auto finish_segment = [&]() __attribute__((always_inline)) {
+        uint64_t need = ballot(count > max(kcq, a.final_keep)) & 0xffffffffull;
+        while (need) {
+            int q = __ffsll((unsigned long long)need) - 1;
+            need &= need - 1;
+            int cnt_q = __shfl(count, q, WAVE);
+            int kc_q = __shfl(kcq, q, WAVE);
+            uint64_t* sq = a.slots + ((size_t)(qbase + 32 * w + q) * a.S + split) * (size_t)a.cap;
+            const int32_t v_q = a.views ? a.views[qbase + 32 * w + q] : a.view;
+            const Shrunk sh = shrink_slot(sq, cnt_q, kc_q, hist, death, v_q);
+            if ((l & 31) == q) count = sh.n;
         }
-        compute(par_tag);
-        ++g;
-        __syncthreads();
+        if (qvalid && l < 32) {
+            a.counts[mq * a.S + split] = count;
+            if (qb_done)
+                for (int s2 = split + 1; s2 < a.S; ++s2) a.counts[mq * a.S + s2] = 0;
+        }
     };
     // per-tile setup: clear the accumulators, fetch the FP8 key scales
     auto tile_start = [&](int tile) __attribute__((always_inline)) {
@@ -790,43 +870,67 @@ __global__ __launch_bounds__((TileGeom<P, SMALL>::THREADS)) __attribute__((amdgp
 #pragma unroll
         for (int b = 0; b < NKB; ++b) acc[b] = f32x16{};
     };
-    // The chunk sequence runs across tiles with the buffers alternating, two
-    // chunks per iteration so each step's buffer is fixed at compile time
-    // (a runtime choice between two instantiations makes the register
-    // allocator copy the accumulators).
-    int tile = tile_begin, c = 0;
-    auto advance = [&]() __attribute__((always_inline)) {
-        if (++c == n_chunks) {
-            epilogue(tile);
-            c = 0;
-            if (++tile < tile_end) tile_start(tile);
+    // Open segments until one has tiles (the first chunk of its first tile
+    // goes to buffer PB); false when the workgroup has no segment left.
+    int tile = 0, c = 0;
+    auto open_segment = [&](auto par_tag) __attribute__((always_inline)) {
+        while (load_segment(seg)) {
+            init_query();
+            if (tile_begin < tile_end) {
+                // earlier epilogues may still read the tile norms the first
+                // loads overwrite
+                if (seg > 0) __syncthreads();
+                issue(par_tag, tile_begin, 0);
+                __syncthreads();
+                tile = tile_begin;
+                c = 0;
+                tile_start(tile);
+                return true;
+            }
+            finish_segment();  // no tiles: count 0
+            ++seg;
         }
+        return false;
     };
-    if (total_g > 0) tile_start(tile);
-    while (g < total_g) {
-        step(std::false_type{}, tile, c);
-        advance();
-        if (g == total_g) break;
-        step(std::true_type{}, tile, c);
-        advance();
-    }
-
-    // Final shrink so each slot hands at most max(kc, final_keep) candidates
-    // to the next stage.
-    {
-        uint64_t need = ballot(count > max(kcq, a.final_keep)) & 0xffffffffull;
-        while (need) {
-            int q = __ffsll((unsigned long long)need) - 1;
-            need &= need - 1;
-            int cnt_q = __shfl(count, q, WAVE);
-            int kc_q = __shfl(kcq, q, WAVE);
-            uint64_t* sq = a.slots + ((size_t)(qbase + 32 * w + q) * a.S + split) * (size_t)a.cap;
-            const int32_t v_q = a.views ? a.views[qbase + 32 * w + q] : a.view;
-            const Shrunk sh = shrink_slot(sq, cnt_q, kc_q, hist, death, v_q);
-            if ((l & 31) == q) count = sh.n;
+    // One chunk from buffer PB: start the loads of the segment's next chunk
+    // into the other buffer (read by every wave before the previous
+    // barrier), run this chunk's MFMAs, then one barrier, which also waits
+    // for those loads.
+    auto step = [&](auto par_tag) __attribute__((always_inline)) {
+        constexpr bool PB = decltype(par_tag)::value;
+        const bool last = c + 1 == n_chunks;
+        if (!last || tile + 1 < tile_end)
+            issue(std::integral_constant<bool, !PB>{}, last ? tile + 1 : tile, last ? 0 : c + 1);
+        compute(par_tag);
+        __syncthreads();
+    };
+    // After a step whose successor reads buffer NB: the tile's epilogue at its
+    // last chunk, the segment's end at its last tile.  Returns false when the
+    // workgroup is done.
+    auto advance = [&](auto nb_tag) __attribute__((always_inline)) {
+        if (++c < n_chunks) return true;
+        epilogue(tile);
+        c = 0;
+        if (++tile < tile_end) {
+            tile_start(tile);
+            return true;
+        }
+        finish_segment();
+        ++seg;
+        return open_segment(nb_tag);
+    };
+    // The chunk sequence runs across tiles (and segments) with the buffers
+    // alternating, two chunks per iteration so each step's buffer is fixed at
+    // compile time (a runtime choice between two instantiations makes the
+    // register allocator copy the accumulators).
+    if (open_segment(std::false_type{})) {
+        for (;;) {
+            step(std::false_type{});
+            if (!advance(std::true_type{})) break;
+            step(std::true_type{});
+            if (!advance(std::false_type{})) break;
         }
     }
-    if (qvalid && l < 32) a.counts[mq * a.S + split] = count;
 }
 
 // ---------------------------------------------------------------------------
@@ -1581,8 +1685,27 @@ atsne_status corpus_prep(const Corpus& c, int64_t r0, int64_t r1, int64_t n_live
     return ATSNE_OK;
 }
 
+// Workgroups of the balanced schedule: one per CU, a whole number per XCD.
+static int stream_wgs() {
+    const int cu = device_cu_count();
+    return cu / KNN_XCDS * KNN_XCDS;
+}
+
+// Splits per query block of the balanced schedule (the most workgroups that
+// cover one query block), 0 when a workgroup's range has too many segments.
+static int stream_splits(int MB, int T, int P) {
+    int S = 1;
+    int4 seg[STREAM_MAX_SEG];
+    for (int p = 0; p < P; ++p) {
+        const int n = stream_segments(p, MB, T, P, seg, STREAM_MAX_SEG);
+        if (n < 0) return 0;
+        for (int i = 0; i < n; ++i) S = std::max(S, seg[i].y + 1);
+    }
+    return S;
+}
+
 SearchPlan plan_search(int prec, int64_t M, int64_t key_lo, int64_t key_hi, int k_max, int kc_max, int s_max,
-                       bool allow_small) {
+                       bool allow_small, bool stream) {
     SearchPlan p;
     p.qb = qb_of(prec);
     p.M = M;
@@ -1605,13 +1728,29 @@ SearchPlan plan_search(int prec, int64_t M, int64_t key_lo, int64_t key_hi, int 
     p.MB = (int)ceil_div(std::max<int64_t>(M, 1), p.qb);
     int S = pick_splits(p.MB, total_tiles, device_cu_count());
     if (s_max > 0) S = std::min(S, s_max);
+    // Balanced schedule when the task grid would run more than one round:
+    // one workgroup per CU (the large geometry holds one per CU), no partial
+    // last round, and at most a few splits per query block (fewer candidate
+    // streams, a smaller select).  It needs its splits to fit under s_max.
+    if (stream && !p.small && key_lo % KT == 0) {
+        const int P = stream_wgs();
+        const int64_t W = (int64_t)p.MB * total_tiles;
+        if (P > 0 && W >= 2 * (int64_t)P) {
+            const int S_stream = stream_splits(p.MB, total_tiles, P);
+            if (S_stream > 0 && (s_max <= 0 || S_stream <= s_max)) {
+                p.stream_wgs = P;
+                S = S_stream;
+            }
+        }
+    }
     p.tiles_per_split = (int)ceil_div(total_tiles, S);
-    p.S = (int)ceil_div(total_tiles, p.tiles_per_split);
+    p.S = p.stream_wgs ? S : (int)ceil_div(total_tiles, p.tiles_per_split);
     Arena a;
     a.take<uint64_t>((size_t)p.MB * p.qb * p.S * p.cap);
     a.take<int32_t>((size_t)p.MB * p.qb * p.S);
     a.take<int32_t>(64);
     a.take<int32_t>(std::max<int64_t>(M, 1));
+    a.take<int4>((size_t)std::max(p.stream_wgs, 1) * (STREAM_MAX_SEG + 1));
     p.ws_bytes = a.used;
     return p;
 }
@@ -1632,6 +1771,7 @@ SearchPlan plan_list_search(int64_t M, int64_t n_blocks, int k_max, int kc_max, 
     a.take<int32_t>((size_t)p.MB * p.qb * p.S);
     a.take<int32_t>(64);
     a.take<int32_t>(std::max<int64_t>(M, 1));
+    a.take<int4>((size_t)STREAM_MAX_SEG + 1);  // (segment table, unused here)
     p.ws_bytes = a.used;
     return p;
 }
@@ -1641,6 +1781,7 @@ struct SearchWs {
     int32_t* counts;
     int32_t* misc;
     int32_t* scan_list;
+    int4* segs;
 };
 
 static SearchWs carve(const SearchPlan& p, void* ws) {
@@ -1650,6 +1791,7 @@ static SearchWs carve(const SearchPlan& p, void* ws) {
     w.counts = a.take<int32_t>((size_t)p.MB * p.qb * p.S);
     w.misc = a.take<int32_t>(64);
     w.scan_list = a.take<int32_t>(std::max<int64_t>(p.M, 1));
+    w.segs = a.take<int4>((size_t)std::max(p.stream_wgs, 1) * (STREAM_MAX_SEG + 1));
     return w;
 }
 
@@ -1690,8 +1832,26 @@ static atsne_status launch_tile(const Corpus& c, const Batch& b, const SearchPla
     if (b.blk_q) t.MB = (int)b.n_blocks;
     t.slots = w.slots;
     t.counts = w.counts;
+    t.segs = nullptr;
+    unsigned n_wg = (unsigned)(t.MB * p.S);
+    // The balanced schedule serves the plain search; a batch whose own
+    // segments would need more splits than the plan (a smaller last batch)
+    // takes the task grid with the plan's splits.
+    if (p.stream_wgs && !p.small && !c.death && !b.blk_q && !b.tau0) {
+        const int T = p.tile_hi - p.tile_lo;
+        const int S_b = (int64_t)t.MB * T >= 2 * (int64_t)p.stream_wgs ? stream_splits(t.MB, T, p.stream_wgs) : 0;
+        if (S_b > 0 && S_b <= p.S) {
+            knn_stream_segments<<<dim3((unsigned)ceil_div(p.stream_wgs, 256)), dim3(256), 0, st>>>(t.MB, T, p.stream_wgs,
+                                                                                              w.segs);
+            ATSNE_LAUNCH_CHECK();
+            t.segs = w.segs;
+            t.final_keep = 0;
+            n_wg = (unsigned)p.stream_wgs;
+        }
+    }
+    if (!t.segs && p.stream_wgs) t.tiles_per_split = (int)ceil_div(p.tile_hi - p.tile_lo, p.S);
     ProfScope ps_(b.tau0 ? "knn_tile_reverse" : (b.blk_q ? "knn_tile_list" : "knn_tile"), st);
-    const dim3 grid((unsigned)(t.MB * p.S));
+    const dim3 grid(n_wg);
     if (p.small) {
         ATSNE_REQUIRE(!c.death && !b.blk_q && !b.tau0 && P != ATSNE_PREC_FP8_E4M3, ATSNE_E_UNSUPPORTED,
                       "the small geometry serves the plain search only");
@@ -1851,17 +2011,18 @@ static atsne_status make_plan(int64_t N, int64_t M, int32_t D, int prec, int k, 
     // batches of query rows.
     const size_t slot_budget = (size_t)2 << 30;
     const int64_t Mq = std::max<int64_t>(M, 1);
-    SearchPlan full = plan_search(prec, Mq, 0, N, k, kc, 0, true);
+    SearchPlan full = plan_search(prec, Mq, 0, N, k, kc, 0, true, true);
     if (full.ws_bytes > slot_budget && full.S > 1) {
         const int64_t s_fit = (int64_t)(slot_budget / ((size_t)Mq * full.cap * 8));
-        full = plan_search(prec, Mq, 0, N, k, kc, (int)std::max<int64_t>(1, std::min<int64_t>(full.S, s_fit)), true);
+        full = plan_search(prec, Mq, 0, N, k, kc, (int)std::max<int64_t>(1, std::min<int64_t>(full.S, s_fit)), true,
+                           true);
     }
     const int qb = qb_of(prec);
     const size_t per_row = (size_t)full.S * full.cap * 8;
     int64_t max_rows = (int64_t)(slot_budget / per_row);
     max_rows = std::max<int64_t>(qb, max_rows / qb * qb);
     p.Mb = std::min<int64_t>(Mq, max_rows);
-    p.sp = p.Mb < Mq ? plan_search(prec, p.Mb, 0, N, k, kc, full.S, true) : full;
+    p.sp = p.Mb < Mq ? plan_search(prec, p.Mb, 0, N, k, kc, full.S, true, true) : full;
     p.total = align_up(p.b_corpus, 256) + p.sp.ws_bytes;
     return ATSNE_OK;
 }

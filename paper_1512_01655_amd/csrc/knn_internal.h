@@ -70,6 +70,10 @@ struct Batch {
 struct SearchPlan {
     int MB = 0, S = 1, tiles_per_split = 1, tile_lo = 0, tile_hi = 0, cap = 0, kc_max = 0, k_max = 0, qb = 256;
     bool small = false;  // 128 x 128 tile geometry (plain search only)
+    // balanced schedule (plain search, large geometry): `stream_wgs`
+    // workgroups, one per CU, each an equal share of the (query block, key
+    // tile) units; 0 = the task grid
+    int stream_wgs = 0;
     int kt = KNN_KT;     // keys per tile
     int64_t M = 0;
     size_t ws_bytes = 0;
@@ -78,9 +82,11 @@ struct SearchPlan {
 // Plan a search of M rows over keys [key_lo, key_hi) of a corpus prepared
 // for `prec`, with at most kc_max candidates and k_max neighbours per row.
 // s_max > 0 caps the number of key splits (to fit a fixed workspace).
-// allow_small lets a small plain search take the 128 x 128 tile geometry.
+// allow_small lets a small plain search take the 128 x 128 tile geometry;
+// stream lets a large plain search take the balanced schedule (one
+// workgroup per CU over equal shares of the work).
 SearchPlan plan_search(int prec, int64_t M, int64_t key_lo, int64_t key_hi, int k_max, int kc_max, int s_max = 0,
-                       bool allow_small = false);
+                       bool allow_small = false, bool stream = false);
 
 // Forward search: exact k nearest neighbours of every batch row (candidate
 // contraction, FP32 re-rank, certificate + exact scan on the FP32 path).
