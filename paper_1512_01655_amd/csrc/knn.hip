@@ -718,13 +718,18 @@ __global__ __launch_bounds__((TileGeom<P, SMALL>::THREADS)) __attribute__((amdgp
         const int64_t tile_row = (int64_t)tile_id(pos) * KT;
         const int64_t co = (int64_t)c * CHUNK_UNITS;
         const uint4* kb = a.Xp + tile_row * row_units + co + krow_;
+        // every address before the first load goes out
+        const uint4* qb = a.Xp + co + ulane;
+        const uint4* qa0 = qb + (uint64_t)qr0 * (uint64_t)row_units;
+        const uint4* qa1 = qb + (uint64_t)qr1 * (uint64_t)row_units;
+        const uint4* qa2 = qb + (uint64_t)qr2 * (uint64_t)row_units;
+        const uint4* qa3 = qb + (uint64_t)qr3 * (uint64_t)row_units;
+        lds_dma16(qa0, qs + 64 * w);
+        lds_dma16(qa1, qs + 64 * (w + TILE_WAVES));
+        lds_dma16(qa2, qs + 64 * (w + 2 * TILE_WAVES));
+        lds_dma16(qa3, qs + 64 * (w + 3 * TILE_WAVES));
 #pragma unroll
         for (int j = 0; j < KT / RSTEP; ++j) lds_dma16(kb + j * kstep_, ks + 64 * (w + TILE_WAVES * j));
-        const uint4* qb = a.Xp + co + ulane;
-        lds_dma16(qb + (uint64_t)qr0 * (uint64_t)row_units, qs + 64 * w);
-        lds_dma16(qb + (uint64_t)qr1 * (uint64_t)row_units, qs + 64 * (w + TILE_WAVES));
-        lds_dma16(qb + (uint64_t)qr2 * (uint64_t)row_units, qs + 64 * (w + 2 * TILE_WAVES));
-        lds_dma16(qb + (uint64_t)qr3 * (uint64_t)row_units, qs + 64 * (w + 3 * TILE_WAVES));
         if (c == 0 && w < KT / 64) {
             lds_dma4(a.norms + tile_row + 64 * w + l, &Kn[pos % 3][64 * w]);
             if constexpr (P == ATSNE_PREC_FP8_E4M3) lds_dma4(a.scales + tile_row + 64 * w + l, &Ksc[pos % 3][64 * w]);
