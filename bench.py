@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--path-only", action="store_true",
                     help="only the FP32 and BF16 steps (no approximate, attractive, ordering, serving legs): the "
                          "command the kernel-trace profile runs")
-    ap.add_argument("--profile-kernel", default=None, choices=["fp32", "bf16", "fp8"],
+    ap.add_argument("--profile-kernel", default=None, choices=["fp32", "bf16", "fp8", "fp32x3"],
                     help="profiling mode: one warm-up and one timed kNN at this precision, then a 1 GiB device "
                          "copy (the reference kernel for scaling HBM byte counters); prints the launch shapes")
     ap.add_argument("--serve-rate", type=float, default=25.0, help="Poisson request rate (req/s)")
@@ -426,6 +426,29 @@ def main():
             "max_abs_dP_vs_exact_same_rows": max_dp_same_rows(torch, rb, r),
         }
         log("bf16: %.1f points/s (x%.2f)" % (vb, vb / value))
+    # The second exact contraction: each FP32 value split into BF16 hi + lo,
+    # three BF16 MFMA products per element pair.  Same certificate (with its
+    # own bound), same FP32 re-rank: its outputs must equal the FP32 path's.
+    rx = run_path(A, torch, Xt, mu, k, "fp32x3", a.steps, a.warmup)
+    vx = N * a.steps / rx["wall"]
+    tx_ms, tx_n = rx["stages"]["knn_tile"]
+    tx_avg = tx_ms / max(tx_n, 1) * 1e-3
+    # matrix-core work: three BF16 products per FP32 product of the contraction
+    ach_x = 3.0 * flop_step * a.steps / max(tx_n, 1) / tx_avg / 1e12
+    same = bool(torch.equal(rx["idx"], r["idx"]) and torch.equal(rx["d2"], r["d2"])
+                and np.array_equal(rx["flags"], r["flags"]))
+    line["exact_fp32x3"] = {
+        "value": round(vx, 1), "ms_per_step": round(1e3 * rx["wall"] / a.steps, 3),
+        "speedup_vs_fp32": round(vx / value, 3), "k_cand": k + max(32, k // 2),
+        "stages_ms": {kname: round(v[0] / a.steps, 3) for kname, v in rx["stages"].items()},
+        "roofline": {"bound": "mfma", "kernel": "knn_tile", "achieved": round(ach_x, 2), "peak": PEAK["bf16"],
+                     "unit": "TFLOP/s", "frac": round(ach_x / PEAK["bf16"], 4),
+                     "traffic": measured_traffic(a.workload, "fp32x3"),
+                     "algorithmic": "3 x 2*N*D BF16 FLOP per query point (hi*hi + hi*lo + lo*hi)"},
+        "outputs_identical_to_fp32": same,
+        "rows_exact_scan": int(((rx["flags"] & 8) > 0).sum()),
+    }
+    log("fp32x3: %.1f points/s (x%.2f), identical to fp32: %s" % (vx, vx / value, same))
     if not (a.no_serve or a.path_only) and a.workload == "imagelike":
         log("serve: Poisson stream at %.0f req/s ..." % a.serve_rate)
         line["serve"] = serve_load(A, torch, X, a.serve_rate, a.serve_requests + 10, 10)

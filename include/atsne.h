@@ -57,7 +57,13 @@ typedef enum atsne_status {
 typedef enum atsne_precision {
     ATSNE_PREC_FP32 = 0,     /* exact path: FP32 MFMA, certified candidate margin */
     ATSNE_PREC_BF16 = 1,     /* BF16 (round-to-nearest-even) MFMA, FP32 accumulate */
-    ATSNE_PREC_FP8_E4M3 = 2  /* OCP FP8 e4m3 with per-row absmax scales, FP32 accumulate */
+    ATSNE_PREC_FP8_E4M3 = 2, /* OCP FP8 e4m3 with per-row absmax scales, FP32 accumulate */
+    ATSNE_PREC_FP32X3 = 3    /* exact path: each FP32 value split into BF16 hi + BF16 lo
+                                (x = hi + lo + r, |r| <= 2^-18 |x|), contraction
+                                hi*hi + hi*lo + lo*hi on BF16 MFMA with FP32 accumulate;
+                                results identical to ATSNE_PREC_FP32 (same FP32 direct-
+                                difference distances, same certificate with this
+                                contraction's error bound, same exact-scan fallback) */
 } atsne_precision;
 
 /* Per-row flags. */

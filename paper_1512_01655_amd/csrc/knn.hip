@@ -77,10 +77,11 @@ __device__ __forceinline__ void lds_dma4(const float* src, float* lds) {
 
 // Elements per 128-byte chunk for each precision.
 __host__ __device__ constexpr int chunk_elems(int prec) {
-    return prec == ATSNE_PREC_FP32 ? 32 : (prec == ATSNE_PREC_BF16 ? 64 : 128);
+    return (prec == ATSNE_PREC_FP32 || prec == ATSNE_PREC_FP32X3) ? 32 : (prec == ATSNE_PREC_BF16 ? 64 : 128);
 }
 __host__ __device__ constexpr int elem_bytes(int prec) {
-    return prec == ATSNE_PREC_FP32 ? 4 : (prec == ATSNE_PREC_BF16 ? 2 : 1);
+    // (FP32X3: a BF16 hi and a BF16 lo per element)
+    return (prec == ATSNE_PREC_FP32 || prec == ATSNE_PREC_FP32X3) ? 4 : (prec == ATSNE_PREC_BF16 ? 2 : 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -159,6 +160,15 @@ __global__ __launch_bounds__(256) void knn_prep(const float* __restrict__ X, int
             static_cast<uint16_t*>(Xp)[row * Dp + d] = h;
             float r = bf16_to_f32(h);
             acc = fmaf(r, r, acc);
+        } else if (P == ATSNE_PREC_FP32X3) {
+            // per 32-element chunk: 64 bytes of hi parts, then 64 bytes of lo
+            // parts of the same elements; the norm is that of the FP32 row
+            const uint16_t h = f32_to_bf16_rne(v);
+            const uint16_t lo = f32_to_bf16_rne(v - bf16_to_f32(h));
+            uint16_t* chunk = static_cast<uint16_t*>(Xp) + row * 2 * (int64_t)Dp + (d >> 5) * 64;
+            chunk[d & 31] = h;
+            chunk[32 + (d & 31)] = lo;
+            acc = fmaf(v, v, acc);
         } else {
             uint8_t q = f32_to_e4m3_rne(v / s);
             static_cast<uint8_t*>(Xp)[row * Dp + d] = q;
@@ -212,6 +222,24 @@ __device__ __forceinline__ float fp32_contraction_bound(int32_t Dp, float nq, fl
     const float gam = 1.05f * (float)(Dp + 2) * u;
     const float sq = sqrtf(nq) + sqrtf(nmax);
     return gam * (sq * sq) + 2.0f * u * (fabsf(dprime) + nq);
+}
+
+// The same bound for the FP32X3 contraction.  With x = h + l + r (h = bf16(x),
+// l = bf16(x - h)): |x - h| <= 2^-9 |x|, |r| <= 2^-18 |x|, so the dropped
+// terms l l' + h r' + r h' + ... of x x' sum to at most 3.01 * 2^-18 |x x'|.
+// Each 32-element chunk's 96 exact BF16 products are summed in FP32 into a
+// fresh partial, and the Dp / 32 partials are added to the running sum one
+// by one; counting 2u per rounding (which also covers truncating adds inside
+// the matrix core), |fl(S) - S| <= (2 (96 + Dp / 32 + 1) u + 3.01 * 2^-18)
+// * 1.01 * sum |x_i x'_i|.  The norms are FP32 sums as on the FP32 path.  A
+// tiny absolute term covers flushed subnormal lo parts.
+__device__ __forceinline__ float x3_contraction_bound(int32_t Dp, float nq, float nmax, float dprime) {
+    const float u = 5.9604645e-8f;
+    const float gam_s = 1.01f * (2.0f * (float)(96 + Dp / 32 + 1) * u + 3.01f * 3.8146973e-6f);
+    const float gam_n = 1.05f * (float)(Dp + 2) * u;
+    const float gam = fmaxf(gam_s, gam_n);
+    const float sq = sqrtf(nq) + sqrtf(nmax);
+    return gam * (sq * sq) + 2.0f * u * (fabsf(dprime) + nq) + (float)(3 * Dp + 2) * 1e-36f;
 }
 
 __device__ __forceinline__ int64_t load_qid(const int32_t* qids, int64_t m0, int64_t m) {
@@ -292,6 +320,26 @@ __device__ __forceinline__ void mfma_fp8_block(f32x16& acc, const uint4 (&a)[4],
         c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(va, vb, c, 0, 0, 0, sa, 0, sb);
     }
     acc = c;
+}
+
+// One FP32X3 key block against the query block over one chunk.  Fragments
+// i = 0, 1 hold the hi parts of the chunk's elements 0-15 and 16-31, i = 2, 3
+// their lo parts.  The chunk's 96 exact BF16 products (per K-step lo*hi +
+// hi*lo + hi*hi) go into a fresh partial, which one FP32 add folds into the
+// running sum: the contraction's rounding error then grows with the number of
+// chunks, not of products.
+template <bool FIRST>
+__device__ __forceinline__ void mfma_x3_block(f32x16& acc, const uint4 (&a)[4], const uint4 (&b)[4]) {
+    f32x16 t = {};
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const bf16x8 bh = __builtin_bit_cast(bf16x8, b[i]), bl = __builtin_bit_cast(bf16x8, b[i + 2]);
+        const bf16x8 ah = __builtin_bit_cast(bf16x8, a[i]), al = __builtin_bit_cast(bf16x8, a[i + 2]);
+        t = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, t, 0, 0, 0);
+        t = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, t, 0, 0, 0);
+        t = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, t, 0, 0, 0);
+    }
+    acc = FIRST ? t : acc + t;
 }
 
 // E8M0 encoding of a power-of-two float scale: its biased exponent.
@@ -750,7 +798,14 @@ __global__ __launch_bounds__((TileGeom<P, SMALL>::THREADS)) __attribute__((amdgp
         uint4 bq[4], ca0[4], ca1[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) bq[i] = Q[qloc * CHUNK_UNITS + (chunk_unit<P>(l, i) ^ sw)];
-        if constexpr (P == ATSNE_PREC_FP8_E4M3) {
+        if constexpr (P == ATSNE_PREC_FP32X3) {
+#pragma unroll
+            for (int b = 0; b < NKB; ++b) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) ca0[i] = K[(32 * b + (l & 31)) * CHUNK_UNITS + (chunk_unit<P>(l, i) ^ sw)];
+                mfma_x3_block<FIRST>(acc[b], ca0, bq);
+            }
+        } else if constexpr (P == ATSNE_PREC_FP8_E4M3) {
 #pragma unroll
             for (int b = 0; b < NKB; ++b) {
 #pragma unroll
@@ -1344,7 +1399,7 @@ __global__ __launch_bounds__(64 * SEL_ROWS) void knn_select(SelArgs a, int kcap)
     uint8_t extra = 0;
     if (n >= k) rank_sort(n, cj, cd, reinterpret_cast<uint64_t*>(dd), sorted);
     const int64_t n_valid = max<int64_t>(0, nl - a.key_lo) - ((q >= a.key_lo && q < nl) ? 1 : 0);
-    if (P == ATSNE_PREC_FP32 && take < n_valid && n >= k) {
+    if ((P == ATSNE_PREC_FP32 || P == ATSNE_PREC_FP32X3) && take < n_valid && n >= k) {
         // Certificate: every non-candidate j has d'_j >= d'(kstar), so its
         // true distance is at least d'(kstar) + n_q - E.  If that exceeds the
         // (k+1)-th exact candidate distance (plus the direct-difference
@@ -1355,7 +1410,8 @@ __global__ __launch_bounds__(64 * SEL_ROWS) void knn_select(SelArgs a, int kcap)
         const float nq = a.norms[q];
         const float nmax = nl > 0 ? a.pmax[nl - 1] : 0.0f;
         const float dthr = key_dist(kstar);
-        const float lb = dthr + nq - fp32_contraction_bound(a.Dp, nq, nmax, dthr);
+        const float lb = dthr + nq - (P == ATSNE_PREC_FP32X3 ? x3_contraction_bound(a.Dp, nq, nmax, dthr)
+                                                             : fp32_contraction_bound(a.Dp, nq, nmax, dthr));
         if (!(lb > dk * (1.0f + 2.0f * TIE_REL))) {
             extra = ATSNE_FLAG_EXACT_SCAN;
             if (l == 0) {
@@ -1617,7 +1673,7 @@ __global__ __launch_bounds__(64) void knn_reverse_merge(RevArgs r) {
 // Host side
 // ---------------------------------------------------------------------------
 static int default_kcand(int prec, int k) {
-    if (prec == ATSNE_PREC_FP32) return k + std::max(32, k / 2);
+    if (prec == ATSNE_PREC_FP32 || prec == ATSNE_PREC_FP32X3) return k + std::max(32, k / 2);
     return 2 * k;
 }
 
@@ -1679,6 +1735,10 @@ atsne_status corpus_prep(const Corpus& c, int64_t r0, int64_t r1, int64_t n_live
         case ATSNE_PREC_BF16:
             knn_prep<ATSNE_PREC_BF16><<<grid, block, 0, st>>>(c.X, c.ld, c.D, c.Dp, r0, r1, n_live, c.Xp, c.norms,
                                                               c.scales);
+            break;
+        case ATSNE_PREC_FP32X3:
+            knn_prep<ATSNE_PREC_FP32X3><<<grid, block, 0, st>>>(c.X, c.ld, c.D, c.Dp, r0, r1, n_live, c.Xp, c.norms,
+                                                                c.scales);
             break;
         default:
             knn_prep<ATSNE_PREC_FP8_E4M3><<<grid, block, 0, st>>>(c.X, c.ld, c.D, c.Dp, r0, r1, n_live, c.Xp,
@@ -1886,6 +1946,8 @@ static atsne_status launch_tile_any(const Corpus& c, const Batch& b, const Searc
             return launch_tile<ATSNE_PREC_FP32>(c, b, p, w, st);
         case ATSNE_PREC_BF16:
             return launch_tile<ATSNE_PREC_BF16>(c, b, p, w, st);
+        case ATSNE_PREC_FP32X3:
+            return launch_tile<ATSNE_PREC_FP32X3>(c, b, p, w, st);
         default:
             return launch_tile<ATSNE_PREC_FP8_E4M3>(c, b, p, w, st);
     }
@@ -1948,12 +2010,15 @@ atsne_status knn_search(const Corpus& c, const Batch& b, const SearchPlan& p, vo
             case ATSNE_PREC_BF16:
                 knn_select<ATSNE_PREC_BF16><<<sel_grid, dim3(64 * rows), lds, st>>>(s, kcap);
                 break;
+            case ATSNE_PREC_FP32X3:
+                knn_select<ATSNE_PREC_FP32X3><<<sel_grid, dim3(64 * rows), lds, st>>>(s, kcap);
+                break;
             default:
                 knn_select<ATSNE_PREC_FP8_E4M3><<<sel_grid, dim3(64 * rows), lds, st>>>(s, kcap);
         }
         ATSNE_LAUNCH_CHECK();
     }
-    if (c.prec == ATSNE_PREC_FP32) {
+    if (c.prec == ATSNE_PREC_FP32 || c.prec == ATSNE_PREC_FP32X3) {
         const int grid = (int)std::min<int64_t>(b.M, 4 * (int64_t)device_cu_count());
         ProfScope ps_("knn_scan", st);
         knn_scan<<<dim3((unsigned)grid), dim3(256), 0, st>>>(s, 32, w.misc + 2);
@@ -1995,7 +2060,8 @@ struct KnnPlan {
 };
 
 static atsne_status make_plan(int64_t N, int64_t M, int32_t D, int prec, int k, int k_cand, KnnPlan& p) {
-    ATSNE_REQUIRE(prec == ATSNE_PREC_FP32 || prec == ATSNE_PREC_BF16 || prec == ATSNE_PREC_FP8_E4M3,
+    ATSNE_REQUIRE(prec == ATSNE_PREC_FP32 || prec == ATSNE_PREC_BF16 || prec == ATSNE_PREC_FP8_E4M3 ||
+                      prec == ATSNE_PREC_FP32X3,
                   ATSNE_E_INVALID_ARG, "unknown precision %d", prec);
     ATSNE_REQUIRE(N >= 2 && N < (1ll << 31) - KT, ATSNE_E_INVALID_ARG, "N=%lld out of range", (long long)N);
     ATSNE_REQUIRE(M >= 0 && M < (1ll << 31), ATSNE_E_INVALID_ARG, "M=%lld out of range", (long long)M);

@@ -58,10 +58,10 @@ def test_host_side_validation():
                                      None) == atsne.E_INVALID_ARG
 
 
-@pytest.mark.parametrize("prec,k,kc", [(0, 90, 0), (1, 90, 0), (2, 150, 0), (0, 90, 90)])
+@pytest.mark.parametrize("prec,k,kc", [(0, 90, 0), (1, 90, 0), (2, 150, 0), (0, 90, 90), (3, 90, 0)])
 def test_workspace_grows_with_candidates(prec, k, kc):
     from paper_1512_01655_amd import atsne
 
-    small = atsne.knn_workspace_size(20000, 20000, 128, k, ["fp32", "bf16", "fp8"][prec], kc)
-    big = atsne.knn_workspace_size(20000, 20000, 128, k, ["fp32", "bf16", "fp8"][prec], 2 * k + 50)
+    small = atsne.knn_workspace_size(20000, 20000, 128, k, ["fp32", "bf16", "fp8", "fp32x3"][prec], kc)
+    big = atsne.knn_workspace_size(20000, 20000, 128, k, ["fp32", "bf16", "fp8", "fp32x3"][prec], 2 * k + 50)
     assert big > small > 0

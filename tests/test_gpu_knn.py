@@ -8,6 +8,8 @@ from tests import parity
 from tests.gpu_common import lib, run_knn, say
 
 pytestmark = pytest.mark.gpu
+# the two exact contractions: FP32 MFMA and the BF16 hi/lo split (FP32X3)
+EXACT = ["fp32", "fp32x3"]
 
 
 @pytest.fixture(scope="module")
@@ -34,35 +36,39 @@ def _compare(A, ora, X, k, prec="fp32", kc=0, qids=None, exact=False):
     return g_fl
 
 
+@pytest.mark.parametrize("prec", EXACT)
 @pytest.mark.parametrize("case", range(7))
-def test_knn_small_ragged(A, ora, case):
+def test_knn_small_ragged(A, ora, case, prec):
     X = datagen.small_cases()[case]
     N = X.shape[0]
     for k in sorted({1, 7, min(90, N - 1), N - 1}):
-        _compare(A, ora, X, k)
+        _compare(A, ora, X, k, prec=prec)
 
 
-def test_knn_config1_full(A, ora):
+@pytest.mark.parametrize("prec", EXACT)
+def test_knn_config1_full(A, ora, prec):
     X = datagen.mixture_isotropic()
-    _compare(A, ora, X, 90)
+    _compare(A, ora, X, 90, prec=prec)
 
 
-def test_knn_config1_kcand_equals_k(A, ora):
+@pytest.mark.parametrize("prec", EXACT)
+def test_knn_config1_kcand_equals_k(A, ora, prec):
     # no candidate margin: the certificate must route uncertain rows to the exact scan
     X = datagen.mixture_isotropic()
-    _compare(A, ora, X, 90, kc=90)
+    _compare(A, ora, X, 90, prec=prec, kc=90)
 
 
-def test_knn_integer_ties_exact(A, ora):
+@pytest.mark.parametrize("prec", EXACT)
+def test_knn_integer_ties_exact(A, ora, prec):
     # small integers: every distance is exact in FP32, so the (d, j) ranking,
     # ties included, must match bit for bit
     rng = np.random.default_rng(3)
     for N, D, k in [(300, 4, 20), (1000, 3, 50), (600, 40, 90)]:
         X = rng.integers(-3, 4, size=(N, D)).astype(np.float32)
-        _compare(A, ora, X, k, exact=True)
+        _compare(A, ora, X, k, prec=prec, exact=True)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8", "fp32x3"])
 def test_knn_representable_exact_all_precisions(A, ora, prec):
     # integers in [-7, 7] with a 7 in every row are exact in FP32, BF16 and
     # (scale 7/448 = 2^-6) FP8 e4m3, so all three contractions are exact
@@ -73,30 +79,33 @@ def test_knn_representable_exact_all_precisions(A, ora, prec):
         _compare(A, ora, X, k, prec=prec, exact=True)
 
 
-def test_knn_duplicates(A, ora):
+@pytest.mark.parametrize("prec", EXACT)
+def test_knn_duplicates(A, ora, prec):
     rng = np.random.default_rng(5)
     base = rng.normal(size=(300, 16)).astype(np.float32)
     X = np.concatenate([base, base, base])[rng.permutation(900)]
-    _compare(A, ora, X, 10, exact=False)
-    g_idx, g_d2, _ = run_knn(A, X, 10)
+    _compare(A, ora, X, 10, prec=prec, exact=False)
+    g_idx, g_d2, _ = run_knn(A, X, 10, prec)
     o_idx, o_d2, _ = ora.knn(X, 10)
     assert np.array_equal(g_idx[:, :2], o_idx[:, :2])  # the two exact copies, lower index first
     assert np.all(g_d2[:, :2] == 0)
 
 
-def test_knn_all_equal(A, ora):
+@pytest.mark.parametrize("prec", EXACT)
+def test_knn_all_equal(A, ora, prec):
     X = np.ones((600, 33), np.float32)
-    g_idx, g_d2, g_fl = run_knn(A, X, 25)
+    g_idx, g_d2, g_fl = run_knn(A, X, 25, prec)
     for i in range(600):
         exp = [j for j in range(27) if j != i][:25]
         assert g_idx[i].tolist() == exp
     assert np.all(g_d2 == 0)
 
 
-def test_knn_subset(A, ora):
+@pytest.mark.parametrize("prec", EXACT)
+def test_knn_subset(A, ora, prec):
     X = datagen.mixture_isotropic()
     q = np.random.default_rng(6).choice(2000, size=333, replace=False).astype(np.int32)
-    _compare(A, ora, X, 90, qids=q)
+    _compare(A, ora, X, 90, prec=prec, qids=q)
 
 
 def test_knn_errors(A):
@@ -122,6 +131,11 @@ def test_knn_config2_sampled(A, ora):
     say("    config2 sample: tie-rule rows %d/200; fp64 rows %d, exact-scan rows %d (of 70000)" % (
         ties, int((g_fl & 1).sum()), int(((g_fl & 8) > 0).sum())))
     assert np.all(np.diff(g_d2, axis=1) >= 0)
+    # the FP32X3 contraction certifies the same candidates: every row's
+    # neighbours, distances and flags are those of the FP32 path
+    x_idx, x_d2, x_fl = run_knn(A, X, 90, "fp32x3")
+    assert np.array_equal(x_idx, g_idx) and np.array_equal(x_d2, g_d2) and np.array_equal(x_fl, g_fl)
+    say("    config2: fp32x3 identical to fp32 on all 70000 rows, exact-scan rows %d" % int(((x_fl & 8) > 0).sum()))
 
 
 def test_knn_bf16_recall_config2(A, ora):
