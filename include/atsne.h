@@ -167,7 +167,8 @@ atsne_status atsne_symmetrize(const int32_t* nbr_idx, const float* P_cond, int64
                               size_t ws_bytes, void* stream);
 
 /* As atsne_symmetrize for conditional rows of varying length given as CSR:
- * in_ptr [N+1] int64, in_col/in_val [in_ptr[N]] (device).  Output capacity
+ * in_ptr [N+1] int64 with in_ptr[0] = 0, in_col/in_val [in_ptr[N]] (device),
+ * columns distinct within a row, in [0, N), no self.  Output capacity
  * 2*in_ptr[N]; nnz_in_host is in_ptr[N] (host copy, so no extra sync). */
 atsne_status atsne_symmetrize_csr(const int64_t* in_ptr, const int32_t* in_col, const float* in_val,
                                   int64_t N, int64_t nnz_in_host, int64_t* row_ptr, int32_t* col, float* val,

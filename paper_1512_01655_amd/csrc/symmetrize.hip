@@ -4,96 +4,33 @@
 // only the per-point conditional rows are stored upstream).  The output is
 // CSR with ascending columns over the union of the neighbour patterns.
 //
-// Device pipeline (HBM/atomic bound, one wave per row where rows are walked):
-//   sym_count    cnt[i] = |N_i| + in-degree(i)          (atomics on cnt[j])
-//   scan         off = exclusive scan of cnt
-//   sym_scatter  row i receives (j, p_{j|i}) in place and, mirrored, row j
-//                receives (i, p_{j|i}) at an atomic cursor
-//   sym_merge    per row: sort by (column, origin), add the at most two
-//                entries of each column, divide by 2N; unique count u[i]
-//   scan         row_ptr = exclusive scan of u
-//   sym_compact  copy the merged rows to their final place
-// Each output value is the sum of at most two addends, so the atomics'
-// arbitrary order does not change any result bit.
+// Device pipeline (HBM bound; one global key sort instead of per-row sorts,
+// so hub rows of the kNN graph cost no more than any other entries):
+//   sym_keys     each conditional entry (i, j, p_{j|i}) becomes two keys,
+//                (row i, column j, own) and (row j, column i, mirrored),
+//                both carrying p_{j|i}
+//   radix sort   of the 2*nnz (key, value) pairs over the 2b+1 key bits
+//                (b bits per index), giving row-major, column-ascending order
+//                with the own half of a column before its mirrored half
+//   sym_heads    per 1024 sorted entries: number of distinct (row, column)
+//   scan         exclusive block offsets (one workgroup)
+//   sym_emit     each distinct (row, column) adds its at most two addends,
+//                scales by 1/(2N) and lands at its CSR position; the first
+//                entry of each row (and every empty row before it) writes
+//                row_ptr
+// All keys are distinct and each output value is the sum of at most two
+// addends, so the result is bit-for-bit deterministic.
 #include <algorithm>
+
+#include <rocprim/device/device_radix_sort.hpp>
 
 #include "common.h"
 #include "wave.h"
 
 namespace atsne {
 
-constexpr int SCAN_BLOCK = 1024;  // elements per scan block (256 threads x 4)
-
-// ---- exclusive scan of int32 counts into int64 offsets (3 phases) ----
-__global__ __launch_bounds__(256) void scan_blocks(const int32_t* __restrict__ in, int64_t n,
-                                                   int64_t* __restrict__ out, int64_t* __restrict__ block_sums) {
-    __shared__ int64_t wsum[4];
-    const int t = threadIdx.x, l = t & 63, w = t >> 6;
-    const int64_t base = (int64_t)blockIdx.x * SCAN_BLOCK + 4 * t;
-    int64_t v[4];
-    int64_t s = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        v[i] = (base + i < n) ? in[base + i] : 0;
-        s += v[i];
-    }
-    // wave inclusive scan of per-thread sums
-    int64_t incl = s;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        int64_t tv = __shfl_up(incl, o, 64);
-        if (l >= o) incl += tv;
-    }
-    if (l == 63) wsum[w] = incl;
-    __syncthreads();
-    int64_t woff = 0;
-    for (int i = 0; i < w; ++i) woff += wsum[i];
-    int64_t run = woff + incl - s;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        if (base + i < n) out[base + i] = run;
-        run += v[i];
-    }
-    if (t == 255) block_sums[blockIdx.x] = woff + incl;
-}
-
-__global__ __launch_bounds__(64) void scan_sums(int64_t* __restrict__ block_sums, int64_t nb, int64_t* __restrict__ total) {
-    // one wave, sequential over chunks of 64 (nb is small)
-    const int l = lane_id();
-    int64_t carry = 0;
-    for (int64_t b0 = 0; b0 < nb; b0 += 64) {
-        int64_t v = (b0 + l < nb) ? block_sums[b0 + l] : 0;
-        int64_t incl = v;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            int64_t tv = __shfl_up(incl, o, 64);
-            if (l >= o) incl += tv;
-        }
-        if (b0 + l < nb) block_sums[b0 + l] = carry + incl - v;
-        carry += __shfl(incl, 63, 64);
-    }
-    if (l == 0) *total = carry;
-}
-
-__global__ __launch_bounds__(256) void scan_add(int64_t* __restrict__ out, int64_t n, const int64_t* __restrict__ block_sums) {
-    const int64_t base = (int64_t)blockIdx.x * SCAN_BLOCK + 4 * threadIdx.x;
-    const int64_t add = block_sums[blockIdx.x];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-        if (base + i < n) out[base + i] += add;
-}
-
-// out[0..n) = exclusive scan of in, out[n] = total.  block_sums: ceil(n/1024) entries.
-static atsne_status exclusive_scan(const int32_t* in, int64_t n, int64_t* out, int64_t* block_sums, hipStream_t st) {
-    const int64_t nb = std::max<int64_t>(1, ceil_div(n, SCAN_BLOCK));
-    scan_blocks<<<dim3((unsigned)nb), dim3(256), 0, st>>>(in, n, out, block_sums);
-    ATSNE_LAUNCH_CHECK();
-    scan_sums<<<dim3(1), dim3(64), 0, st>>>(block_sums, nb, out + n);
-    ATSNE_LAUNCH_CHECK();
-    scan_add<<<dim3((unsigned)nb), dim3(256), 0, st>>>(out, n, block_sums);
-    ATSNE_LAUNCH_CHECK();
-    return ATSNE_OK;
-}
+constexpr int SYM_BLOCK = 1024;  // sorted entries per sym_heads / sym_emit workgroup (256 threads x 4)
+constexpr uint64_t SYM_NONE = ~0ull;  // sentinel key: (SYM_NONE >> 1) equals no real (row, column) pair
 
 // Row extent of the conditional input: CSR (in_ptr) or fixed k.
 struct RowsIn {
@@ -103,166 +40,177 @@ struct RowsIn {
     __device__ __forceinline__ int64_t end(int64_t i) const { return ptr ? ptr[i + 1] : (i + 1) * k; }
 };
 
-__global__ __launch_bounds__(256) void sym_count(RowsIn rin, const int32_t* __restrict__ col, int64_t N,
-                                                 int32_t* __restrict__ cnt) {
+// Key layout: row << s | column << 1 | origin (0 own, 1 mirrored), s = b + 1.
+__global__ __launch_bounds__(256) void sym_keys(RowsIn rin, const int32_t* __restrict__ col,
+                                                const float* __restrict__ val, int64_t N, int s,
+                                                ulonglong2* __restrict__ key, float2* __restrict__ kval) {
     const int l = lane_id();
     const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= N) return;
     const int64_t b = rin.begin(i), e = rin.end(i);
-    for (int64_t t = b + l; t < e; t += WAVE) atomicAdd(&cnt[col[t]], 1);
-    if (l == 0) atomicAdd(&cnt[i], (int32_t)(e - b));
-}
-
-// Entry key: column in the high bits, origin (0 own, 1 mirrored) in bit 0.
-__global__ __launch_bounds__(256) void sym_scatter(RowsIn rin, const int32_t* __restrict__ col,
-                                                   const float* __restrict__ val, int64_t N,
-                                                   const int64_t* __restrict__ off, int32_t* __restrict__ fill,
-                                                   int64_t* __restrict__ tkey, float* __restrict__ tval) {
-    const int l = lane_id();
-    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (i >= N) return;
-    const int64_t b = rin.begin(i), e = rin.end(i);
+    const uint64_t ui = (uint64_t)i;
     for (int64_t t = b + l; t < e; t += WAVE) {
-        const int32_t j = col[t];
+        const uint64_t j = (uint64_t)(uint32_t)col[t];
         const float p = val[t];
-        const int64_t own = off[i] + (t - b);
-        tkey[own] = ((int64_t)j << 1);
-        tval[own] = p;
-        const int64_t lenj = rin.end(j) - rin.begin(j);
-        const int64_t mir = off[j] + lenj + atomicAdd(&fill[j], 1);
-        tkey[mir] = ((int64_t)i << 1) | 1;
-        tval[mir] = p;
+        key[t] = make_ulonglong2((ui << s) | (j << 1), (j << s) | (ui << 1) | 1);
+        kval[t] = make_float2(p, p);
     }
 }
 
-constexpr int MERGE_LDS = 2048;
-
-__device__ __forceinline__ void row_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    __builtin_amdgcn_wave_barrier();
+// Sum of v over a 256-thread workgroup (result valid in every thread).
+__device__ __forceinline__ int block_sum256(int v, int* red) {
+    const int w = threadIdx.x >> 6;
+    v = wave_sum(v);
+    if (lane_id() == 0) red[w] = v;
+    __syncthreads();
+    return red[0] + red[1] + red[2] + red[3];
 }
 
-// In-place ascending sort of n (key, value) pairs by one wave: bitonic
-// network whose comparators all point the same way (a flip step, then
-// half-cleaners), so positions >= n act as +inf and are never touched.
-// Works on LDS or global memory alike.
-__device__ void wave_bitonic_sort(int64_t* key, float* val, int n) {
-    const int l = lane_id();
-    int P = 1;
-    while (P < n) P <<= 1;
-    auto cmpswap = [&](int a, int b) {
-        if (b < n) {
-            int64_t ka = key[a], kb = key[b];
-            if (ka > kb) {
-                float va = val[a], vb = val[b];
-                key[a] = kb;
-                key[b] = ka;
-                val[a] = vb;
-                val[b] = va;
+__global__ __launch_bounds__(256) void sym_heads(const uint64_t* __restrict__ key, int64_t n,
+                                                 int64_t* __restrict__ block_sums) {
+    __shared__ int red[4];
+    const int64_t base = (int64_t)blockIdx.x * SYM_BLOCK + 4 * threadIdx.x;
+    int c = 0;
+    if (base < n) {
+        uint64_t prev = base > 0 ? key[base - 1] >> 1 : SYM_NONE;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (base + q < n) {
+                const uint64_t kq = key[base + q] >> 1;
+                c += kq != prev;
+                prev = kq;
             }
         }
-    };
-    for (int size = 2; size <= P; size <<= 1) {
-        const int half = size >> 1;
-        for (int t = l; t < P / 2; t += WAVE) {
-            const int blk = t / half, o = t % half;
-            cmpswap(blk * size + o, blk * size + size - 1 - o);
-        }
-        row_sync();
-        for (int stride = half >> 1; stride > 0; stride >>= 1) {
-            for (int t = l; t < P / 2; t += WAVE) {
-                const int a = (t / stride) * (2 * stride) + (t % stride);
-                cmpswap(a, a + stride);
+    }
+    const int tot = block_sum256(c, red);
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
+}
+
+// In-place exclusive scan of nb block counts by one workgroup (each thread
+// takes a contiguous run); *total receives the sum.
+__global__ __launch_bounds__(1024) void sym_scan_blocks(int64_t* __restrict__ bs, int64_t nb, int64_t* __restrict__ total) {
+    __shared__ int64_t wsum[16];
+    const int t = threadIdx.x, l = t & 63, w = t >> 6;
+    const int64_t per = (nb + 1023) / 1024;
+    const int64_t b0 = std::min<int64_t>(nb, t * per), b1 = std::min<int64_t>(nb, b0 + per);
+    int64_t s = 0;
+    for (int64_t b = b0; b < b1; ++b) s += bs[b];
+    int64_t incl = s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t tv = __shfl_up(incl, o, 64);
+        if (l >= o) incl += tv;
+    }
+    if (l == 63) wsum[w] = incl;
+    __syncthreads();
+    int64_t woff = 0;
+    for (int i = 0; i < w; ++i) woff += wsum[i];
+    int64_t run = woff + incl - s;
+    for (int64_t b = b0; b < b1; ++b) {
+        const int64_t v = bs[b];
+        bs[b] = run;
+        run += v;
+    }
+    if (t == 1023) *total = woff + incl;
+}
+
+struct EmitArgs {
+    const uint64_t* key;
+    const float* v;
+    int64_t n, N;
+    int s;
+    uint64_t cmask;  // (1 << b) - 1
+    const int64_t* block_off;
+    float inv_norm;
+    int64_t* row_ptr;
+    int32_t* col;
+    float* val;
+};
+
+__global__ __launch_bounds__(256) void sym_emit(EmitArgs a) {
+    __shared__ int64_t wsum[4];
+    const int t = threadIdx.x, l = t & 63, w = t >> 6;
+    const int64_t base = (int64_t)blockIdx.x * SYM_BLOCK + 4 * t;
+    // kk[0] = predecessor, kk[1..4] = own entries, kk[5] = successor
+    uint64_t kk[6];
+    int c = 0;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        const int64_t e = base + q - 1;
+        kk[q] = (base < a.n && e >= 0 && e < a.n) ? a.key[e] : SYM_NONE;
+    }
+    bool h[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        h[q] = base + q < a.n && (kk[q + 1] >> 1) != (kk[q] >> 1);
+        c += h[q];
+    }
+    int64_t incl = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t tv = __shfl_up(incl, o, 64);
+        if (l >= o) incl += tv;
+    }
+    if (l == 63) wsum[w] = incl;
+    __syncthreads();
+    if (base >= a.n) return;
+    int64_t woff = 0;
+    for (int i = 0; i < w; ++i) woff += wsum[i];
+    int64_t pos = a.block_off[blockIdx.x] + woff + incl - c;
+    int64_t prow = base > 0 ? (int64_t)(kk[0] >> a.s) : -1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t e = base + q;
+        if (e < a.n) {
+            const uint64_t kq = kk[q + 1];
+            const int64_t row = (int64_t)(kq >> a.s);
+            // rows (prow, row] start here: row's first entry and the empty rows before it
+            for (int64_t r = prow + 1; r <= std::min(row, a.N - 1); ++r) a.row_ptr[r] = pos;
+            prow = row;
+            if (h[q]) {
+                float x = a.v[e];
+                if ((kk[q + 2] >> 1) == (kq >> 1)) x += a.v[e + 1];  // own + mirrored
+                a.col[pos] = (int32_t)((kq >> 1) & a.cmask);
+                a.val[pos] = x * a.inv_norm;
+                ++pos;
             }
-            row_sync();
+            if (e == a.n - 1)  // rows after the last stored row are empty
+                for (int64_t r = row + 1; r < a.N; ++r) a.row_ptr[r] = pos;
         }
     }
 }
 
-// Per row: sort entries by key (column, origin), fold the mirrored half of a
-// column into its own entry, write the merged row at off[i] into mcol/mval
-// and its length into u[i].  Rows longer than MERGE_LDS (hubs of the kNN
-// graph) are sorted in place in the global scratch.
-__global__ __launch_bounds__(64) void sym_merge(const int64_t* __restrict__ off, int64_t N,
-                                                int64_t* __restrict__ tkey, float* __restrict__ tval,
-                                                float inv_norm, int32_t* __restrict__ mcol,
-                                                float* __restrict__ mval, int32_t* __restrict__ u) {
-    __shared__ int64_t skey[MERGE_LDS];
-    __shared__ float sval[MERGE_LDS];
-    const int l = lane_id();
-    const int64_t i = blockIdx.x;
-    if (i >= N) return;
-    const int64_t b = off[i];
-    const int n = (int)(off[i + 1] - b);
-    int64_t* K = tkey + b;
-    float* V = tval + b;
-    if (n <= MERGE_LDS) {
-        for (int t = l; t < n; t += WAVE) {
-            skey[t] = K[t];
-            sval[t] = V[t];
-        }
-        row_sync();
-        K = skey;
-        V = sval;
-    }
-    wave_bitonic_sort(K, V, n);
-    // an entry whose column equals its predecessor's is the mirrored half
-    // of that column and is folded into it (own + mirrored, fixed order)
-    int uniq = 0;
-    for (int r0 = 0; r0 < n; r0 += WAVE) {
-        const int r = r0 + l;
-        bool head = false;
-        int64_t kr = 0;
-        if (r < n) {
-            kr = K[r];
-            head = (r == 0) || ((K[r - 1] >> 1) != (kr >> 1));
-        }
-        const uint64_t m = ballot(head);
-        if (head) {
-            float v = V[r];
-            if (r + 1 < n && (K[r + 1] >> 1) == (kr >> 1)) v += V[r + 1];
-            const int pos = uniq + __popcll(m & lanemask_lt());
-            mcol[b + pos] = (int32_t)(kr >> 1);
-            mval[b + pos] = v * inv_norm;
-        }
-        uniq += __popcll(m);
-    }
-    if (l == 0) u[i] = uniq;
-}
-
-__global__ __launch_bounds__(256) void sym_compact(const int64_t* __restrict__ off, const int64_t* __restrict__ row_ptr,
-                                                   int64_t N, const int32_t* __restrict__ mcol,
-                                                   const float* __restrict__ mval, int32_t* __restrict__ col,
-                                                   float* __restrict__ val) {
-    const int l = lane_id();
-    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (i >= N) return;
-    const int64_t src = off[i], dst = row_ptr[i], n = row_ptr[i + 1] - dst;
-    for (int64_t t = l; t < n; t += WAVE) {
-        col[dst + t] = mcol[src + t];
-        val[dst + t] = mval[src + t];
-    }
+__global__ __launch_bounds__(256) void sym_zero_rows(int64_t* __restrict__ row_ptr, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) row_ptr[i] = 0;
 }
 
 struct SymPlan {
-    int64_t N, nnz_in, nb;
-    size_t total;
+    int64_t N, nnz_in, n2, nb;
+    int b;  // bits per index
+    size_t sort_bytes, total;
 };
 
 static void sym_plan(int64_t N, int64_t nnz_in, SymPlan& p) {
     p.N = N;
     p.nnz_in = nnz_in;
-    p.nb = std::max<int64_t>(1, ceil_div(N, SCAN_BLOCK));
+    p.n2 = 2 * nnz_in;
+    p.nb = std::max<int64_t>(1, ceil_div(p.n2, SYM_BLOCK));
+    p.b = N > 1 ? 64 - __builtin_clzll((unsigned long long)(N - 1)) : 1;
+    p.sort_bytes = 0;
+    rocprim::double_buffer<uint64_t> kb(nullptr, nullptr);
+    rocprim::double_buffer<float> vb(nullptr, nullptr);
+    (void)rocprim::radix_sort_pairs(nullptr, p.sort_bytes, kb, vb, (size_t)std::max<int64_t>(p.n2, 1), 0,
+                                    (unsigned)(2 * p.b + 1));
+    p.sort_bytes = std::max<size_t>(p.sort_bytes, 1);
+    const int64_t n2 = std::max<int64_t>(p.n2, 1);
     Arena a;
-    a.take<int32_t>(N);            // cnt
-    a.take<int32_t>(N);            // fill
-    a.take<int32_t>(N);            // u
-    a.take<int64_t>(N + 1);        // off
-    a.take<int64_t>(p.nb);         // block sums
-    a.take<int64_t>(2 * nnz_in);   // tkey
-    a.take<float>(2 * nnz_in);     // tval
-    a.take<int32_t>(2 * nnz_in);   // mcol
-    a.take<float>(2 * nnz_in);     // mval
+    a.take<uint64_t>(n2);        // keys (ping)
+    a.take<uint64_t>(n2);        // keys (pong)
+    a.take<float>(n2);           // values (ping)
+    a.take<float>(n2);           // values (pong)
+    a.take<int64_t>(p.nb);       // block offsets
+    a.take<char>(p.sort_bytes);  // radix sort temporary storage
     p.total = a.used;
 }
 
@@ -270,31 +218,39 @@ static atsne_status sym_run(const SymPlan& p, RowsIn rin, const int32_t* in_col,
                             int64_t* row_ptr, int32_t* col, float* val, int64_t* nnz_host, void* wsp,
                             hipStream_t st) {
     Arena a(wsp, p.total);
-    int32_t* cnt = a.take<int32_t>(p.N);
-    int32_t* fill = a.take<int32_t>(p.N);
-    int32_t* u = a.take<int32_t>(p.N);
-    int64_t* off = a.take<int64_t>(p.N + 1);
+    const int64_t n2 = std::max<int64_t>(p.n2, 1);
+    uint64_t* k0 = a.take<uint64_t>(n2);
+    uint64_t* k1 = a.take<uint64_t>(n2);
+    float* v0 = a.take<float>(n2);
+    float* v1 = a.take<float>(n2);
     int64_t* bsum = a.take<int64_t>(p.nb);
-    int64_t* tkey = a.take<int64_t>(2 * p.nnz_in);
-    float* tval = a.take<float>(2 * p.nnz_in);
-    int32_t* mcol = a.take<int32_t>(2 * p.nnz_in);
-    float* mval = a.take<float>(2 * p.nnz_in);
+    void* sort_tmp = a.take<char>(p.sort_bytes);
     const int64_t N = p.N;
     ProfScope ps_("sym_total", st);
-    ATSNE_HIP(hipMemsetAsync(cnt, 0, (size_t)N * 4, st));
-    ATSNE_HIP(hipMemsetAsync(fill, 0, (size_t)N * 4, st));
-    const dim3 g4((unsigned)ceil_div(N, 4)), b256(256);
-    sym_count<<<g4, b256, 0, st>>>(rin, in_col, N, cnt);
-    ATSNE_LAUNCH_CHECK();
-    ATSNE_TRY(exclusive_scan(cnt, N, off, bsum, st));
-    sym_scatter<<<g4, b256, 0, st>>>(rin, in_col, in_val, N, off, fill, tkey, tval);
-    ATSNE_LAUNCH_CHECK();
-    const float inv_norm = (float)(1.0 / (2.0 * (double)N));
-    sym_merge<<<dim3((unsigned)N), dim3(64), 0, st>>>(off, N, tkey, tval, inv_norm, mcol, mval, u);
-    ATSNE_LAUNCH_CHECK();
-    ATSNE_TRY(exclusive_scan(u, N, row_ptr, bsum, st));
-    sym_compact<<<g4, b256, 0, st>>>(off, row_ptr, N, mcol, mval, col, val);
-    ATSNE_LAUNCH_CHECK();
+    if (p.n2 == 0) {
+        sym_zero_rows<<<dim3((unsigned)ceil_div(N + 1, 256)), dim3(256), 0, st>>>(row_ptr, N + 1);
+        ATSNE_LAUNCH_CHECK();
+    } else {
+        const int s = p.b + 1;
+        sym_keys<<<dim3((unsigned)ceil_div(N, 4)), dim3(256), 0, st>>>(rin, in_col, in_val, N, s,
+                                                                       reinterpret_cast<ulonglong2*>(k0),
+                                                                       reinterpret_cast<float2*>(v0));
+        ATSNE_LAUNCH_CHECK();
+        rocprim::double_buffer<uint64_t> kb(k0, k1);
+        rocprim::double_buffer<float> vb(v0, v1);
+        size_t sort_bytes = p.sort_bytes;
+        ATSNE_HIP(rocprim::radix_sort_pairs(sort_tmp, sort_bytes, kb, vb, (size_t)p.n2, 0, (unsigned)(2 * p.b + 1),
+                                            st));
+        const uint64_t* K = kb.current();
+        const float* V = vb.current();
+        sym_heads<<<dim3((unsigned)p.nb), dim3(256), 0, st>>>(K, p.n2, bsum);
+        ATSNE_LAUNCH_CHECK();
+        sym_scan_blocks<<<dim3(1), dim3(1024), 0, st>>>(bsum, p.nb, row_ptr + N);
+        ATSNE_LAUNCH_CHECK();
+        EmitArgs e{K, V, p.n2, N, s, (1ull << p.b) - 1, bsum, (float)(1.0 / (2.0 * (double)N)), row_ptr, col, val};
+        sym_emit<<<dim3((unsigned)p.nb), dim3(256), 0, st>>>(e);
+        ATSNE_LAUNCH_CHECK();
+    }
     ATSNE_HIP(hipMemcpyAsync(nnz_host, row_ptr + N, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     ps_.stop();
     ATSNE_HIP(hipStreamSynchronize(st));

@@ -161,6 +161,39 @@ def test_symmetrize_csr_variable_rows(A, ora):
     _check_sym_equal(N, (rp.cpu().numpy(), c.cpu().numpy(), v.cpu().numpy()), o)
 
 
+def test_symmetrize_csr_empty_rows(A, ora):
+    # empty rows at both ends and in runs, rows that only receive mirrored
+    # entries, and rows that neither own nor receive any (row_ptr gaps)
+    rng = np.random.default_rng(14)
+    N = 2500
+    lens = rng.integers(0, 12, size=N)
+    lens[:3] = 0
+    lens[-5:] = 0
+    lens[700:900] = 0
+    ptr = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    pool = np.arange(N // 2)  # columns only in the first half: the rest receive nothing
+    col = np.concatenate([rng.choice(pool[pool != i], size=lens[i], replace=False)
+                          for i in range(N)]).astype(np.int32)
+    val = rng.uniform(0.01, 1.0, size=ptr[-1]).astype(np.float32)
+    say("  symmetrize_csr N=%d nnz=%d" % (N, ptr[-1]))
+    rp, c, v = A.symmetrize_csr(torch.from_numpy(ptr).cuda(), torch.from_numpy(col).cuda(),
+                                torch.from_numpy(val).cuda())
+    torch.cuda.synchronize()
+    o = ora.symmetrize_csr(ptr, col, val.astype(np.float64), N)
+    _check_sym_equal(N, (rp.cpu().numpy(), c.cpu().numpy(), v.cpu().numpy()), o)
+
+
+def test_symmetrize_csr_no_entries(A):
+    N = 40
+    ptr = torch.zeros(N + 1, dtype=torch.int64, device="cuda")
+    dummy_c = torch.zeros(1, dtype=torch.int32, device="cuda")
+    dummy_v = torch.zeros(1, dtype=torch.float32, device="cuda")
+    rp, c, v = A.symmetrize_csr(ptr, dummy_c, dummy_v)
+    torch.cuda.synchronize()
+    assert rp.cpu().tolist() == [0] * (N + 1)
+    assert c.numel() == 0 and v.numel() == 0
+
+
 def _pipeline_check(A, ora, X, mu, rows=None):
     N = X.shape[0]
     K = int(math.floor(3 * mu))
