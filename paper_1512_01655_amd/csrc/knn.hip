@@ -540,7 +540,24 @@ __host__ __device__ inline int stream_segments(int p, int MB, int T, int P, int4
         out[n++] = make_int4(qb, p - stream_owner((int64_t)qb * T, W, P), tb, te);
         u += te - tb;
     }
-    return u < u1 ? -1 : n;
+    if (u < u1) return -1;
+    // Run the segments by first tile (longer first on a tie), not in unit
+    // order: every workgroup then starts at key tile 0 and, since all ranges
+    // have the same length (to one unit), the workgroups of an XCD walk the
+    // key tiles nearly in step, in at most two groups a fixed number of tiles
+    // apart, so most key chunks come from memory once per group and from the
+    // XCD's L2 for the other workgroups.  The order of a workgroup's segments
+    // does not change any slot.
+    for (int i = 1; i < n; ++i) {
+        const int4 x = out[i];
+        int j = i;
+        while (j > 0 && (out[j - 1].z > x.z || (out[j - 1].z == x.z && out[j - 1].w - out[j - 1].z < x.w - x.z))) {
+            out[j] = out[j - 1];
+            --j;
+        }
+        out[j] = x;
+    }
+    return n;
 }
 
 // One thread per workgroup of the balanced schedule writes its segment list.
@@ -1151,74 +1168,50 @@ __device__ void finalize_row(const float* __restrict__ X, int64_t ld, int32_t D,
     finalize_sorted(X, ld, D, xq_g, n, k, sorted, dd, out_idx, out_d2, flag_out, extra_flags);
 }
 
-// Exact FP32 direct-difference distances from query q to the n candidates in
-// cj (wave-parallel over dimensions, butterfly reduction), into cd.
+// Exact FP32 direct-difference squared distances |x_q - x_j|^2 for G rows at
+// once, in the one summation order every kernel that reports a distance
+// uses: lane l accumulates the elements d = l, l + 64, ... in increasing
+// order with one fma each, and the 64 lane partials are then added by a
+// butterfly.  The G rows' loads are in flight together; every lane
+// receives the G sums.
+template <int G>
+__device__ __forceinline__ void direct_group(const float* __restrict__ xq, const float* const (&xr)[G], int32_t D,
+                                             float (&out)[G]) {
+    const int l = lane_id();
+#pragma unroll
+    for (int e = 0; e < G; ++e) out[e] = 0.f;
+    for (int d = l; d < D; d += WAVE) {
+        const float q = xq[d];
+        float xv[G];
+#pragma unroll
+        for (int e = 0; e < G; ++e) xv[e] = xr[e][d];
+#pragma unroll
+        for (int e = 0; e < G; ++e) {
+            const float t = q - xv[e];
+            out[e] = fmaf(t, t, out[e]);
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < G; ++e) out[e] = wave_sum(out[e]);
+}
+
+// Exact FP32 direct-difference distances from query xq to the n candidates
+// in cj, into cd, sixteen candidates at a time (a short last group repeats
+// its last candidate and drops the copies).
 __device__ void direct_distances(const float* __restrict__ X, int64_t ld, int32_t D, const float* __restrict__ xq,
                                  int n, const int32_t* cj, float* cd) {
     const int l = lane_id();
-    int c = 0;
-    // eight candidates at a time keep eight row loads in flight per lane;
-    // every candidate's sum (lane-strided partials, then the butterfly) is
-    // the same arithmetic whatever the group size
-    for (; c + 8 <= n; c += 8) {
-        const float* xr[8];
+    for (int c = 0; c < n; c += 16) {
+        const float* xr[16];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) xr[e] = X + (int64_t)cj[c + e] * ld;
-        float acc[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) acc[e] = 0.f;
-        for (int d = l; d < D; d += WAVE) {
-            const float q = xq[d];
-            float xv[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) xv[e] = xr[e][d];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const float t = q - xv[e];
-                acc[e] = fmaf(t, t, acc[e]);
-            }
-        }
-#pragma unroll
-        for (int e = 0; e < 8; ++e) acc[e] = wave_sum(acc[e]);
+        for (int e = 0; e < 16; ++e) xr[e] = X + (int64_t)cj[min(c + e, n - 1)] * ld;
+        float acc[16];
+        direct_group<16>(xq, xr, D, acc);
         if (l == 0) {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) cd[c + e] = acc[e];
+            for (int e = 0; e < 16; ++e)
+                if (c + e < n) cd[c + e] = acc[e];
         }
-    }
-    for (; c + 4 <= n; c += 4) {
-        const float* x0 = X + (int64_t)cj[c] * ld;
-        const float* x1 = X + (int64_t)cj[c + 1] * ld;
-        const float* x2 = X + (int64_t)cj[c + 2] * ld;
-        const float* x3 = X + (int64_t)cj[c + 3] * ld;
-        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-        for (int d = l; d < D; d += WAVE) {
-            float q = xq[d];
-            float t0 = q - x0[d], t1 = q - x1[d], t2 = q - x2[d], t3 = q - x3[d];
-            a0 = fmaf(t0, t0, a0);
-            a1 = fmaf(t1, t1, a1);
-            a2 = fmaf(t2, t2, a2);
-            a3 = fmaf(t3, t3, a3);
-        }
-        a0 = wave_sum(a0);
-        a1 = wave_sum(a1);
-        a2 = wave_sum(a2);
-        a3 = wave_sum(a3);
-        if (l == 0) {
-            cd[c] = a0;
-            cd[c + 1] = a1;
-            cd[c + 2] = a2;
-            cd[c + 3] = a3;
-        }
-    }
-    for (; c < n; ++c) {
-        const float* x0 = X + (int64_t)cj[c] * ld;
-        float a0 = 0.f;
-        for (int d = l; d < D; d += WAVE) {
-            float t0 = xq[d] - x0[d];
-            a0 = fmaf(t0, t0, a0);
-        }
-        a0 = wave_sum(a0);
-        if (l == 0) cd[c] = a0;
     }
     wave_sync();
 }
@@ -1334,6 +1327,7 @@ __global__ __launch_bounds__(64 * SEL_ROWS) void knn_select(SelArgs a, int kcap)
             if (key <= ks) {
                 int p = atomicAdd(&ncand, 1);
                 cj[p] = key_index(key);
+                cd[p] = key_dist(key);
             }
         });
         wave_sync();
@@ -1388,7 +1382,45 @@ __global__ __launch_bounds__(64 * SEL_ROWS) void knn_select(SelArgs a, int kcap)
     }
     const int n = ncand;
     const float* xq = a.X + q * a.ld;
-    direct_distances(a.X, a.ld, a.D, xq, n, cj, cd);
+    const float nq = a.norms ? a.norms[q] : 0.0f;
+    const float nmax = (a.pmax && nl > 0) ? a.pmax[nl - 1] : 0.0f;
+    // ne: the candidates whose exact distance is computed.  On the exact
+    // contractions the key code d' bounds each distance within the
+    // contraction error E(d') (monotone in d'), so only candidates whose
+    // lower bound d' + n_q - E(d') can reach the (k+1)-th exact distance
+    // need it: the k+1 smallest d' are computed first, their largest exact
+    // distance (times 1 + 4 TIE_REL, which covers the direct-difference
+    // error of both orderings) caps the (k+1)-th, and every candidate whose
+    // lower bound exceeds the cap is strictly beyond the (k+1)-th under the
+    // FP32 and the FP64 ordering alike.  The k + 1 best, the tie test, the
+    // FP64 re-rank and the certificate are therefore those of all n.
+    int ne = n;
+    if ((P == ATSNE_PREC_FP32 || P == ATSNE_PREC_FP32X3) && a.norms && a.pmax && n > k + 1) {
+        rank_sort(n, cj, cd, reinterpret_cast<uint64_t*>(dd), sorted);  // by (d', j)
+        for (int c = l; c < n; c += WAVE) cj[c] = key_index(sorted[c]);
+        wave_sync();
+        direct_distances(a.X, a.ld, a.D, xq, k + 1, cj, cd);
+        float mx = 0.0f;
+        for (int c = l; c < k + 1; c += WAVE) mx = fmaxf(mx, cd[c]);
+        const float cap = wave_max(mx) * (1.0f + 4.0f * TIE_REL);
+        int last = k;
+        for (int c0 = k + 1; c0 < n; c0 += WAVE) {
+            const int c = c0 + l;
+            bool in = false;
+            if (c < n) {
+                const float dp = key_dist(sorted[c]);
+                const float E = P == ATSNE_PREC_FP32X3 ? x3_contraction_bound(a.Dp, nq, nmax, dp)
+                                                       : fp32_contraction_bound(a.Dp, nq, nmax, dp);
+                in = !(dp + nq - E > cap);
+            }
+            const uint64_t bm = ballot(in);
+            if (bm) last = c0 + 63 - __clzll(bm);
+        }
+        ne = last + 1;
+        direct_distances(a.X, a.ld, a.D, xq, ne - (k + 1), cj + k + 1, cd + k + 1);
+    } else {
+        direct_distances(a.X, a.ld, a.D, xq, n, cj, cd);
+    }
     if (n < k) {  // fewer keys than requested neighbours (caller error): pad
         for (int r = l; r < k; r += WAVE) {
             out_idx[r] = -1;
@@ -1397,7 +1429,7 @@ __global__ __launch_bounds__(64 * SEL_ROWS) void knn_select(SelArgs a, int kcap)
     }
 
     uint8_t extra = 0;
-    if (n >= k) rank_sort(n, cj, cd, reinterpret_cast<uint64_t*>(dd), sorted);
+    if (n >= k) rank_sort(ne, cj, cd, reinterpret_cast<uint64_t*>(dd), sorted);
     const int64_t n_valid = max<int64_t>(0, nl - a.key_lo) - ((q >= a.key_lo && q < nl) ? 1 : 0);
     if ((P == ATSNE_PREC_FP32 || P == ATSNE_PREC_FP32X3) && take < n_valid && n >= k) {
         // Certificate: every non-candidate j has d'_j >= d'(kstar), so its
@@ -1405,10 +1437,8 @@ __global__ __launch_bounds__(64 * SEL_ROWS) void knn_select(SelArgs a, int kcap)
         // (k+1)-th exact candidate distance (plus the direct-difference
         // error), the candidates hold the true k+1 nearest and the row's
         // ranking, tie decision included, is that of a full scan.
-        const int rk = n > k ? k : k - 1;
+        const int rk = ne > k ? k : k - 1;
         const float dk = key_dist(sorted[rk]);
-        const float nq = a.norms[q];
-        const float nmax = nl > 0 ? a.pmax[nl - 1] : 0.0f;
         const float dthr = key_dist(kstar);
         const float lb = dthr + nq - (P == ATSNE_PREC_FP32X3 ? x3_contraction_bound(a.Dp, nq, nmax, dthr)
                                                              : fp32_contraction_bound(a.Dp, nq, nmax, dthr));
@@ -1421,7 +1451,7 @@ __global__ __launch_bounds__(64 * SEL_ROWS) void knn_select(SelArgs a, int kcap)
         }
     }
     if (n >= k)
-        finalize_sorted(a.X, a.ld, a.D, xq, n, k, sorted, dd, out_idx, out_d2,
+        finalize_sorted(a.X, a.ld, a.D, xq, ne, k, sorted, dd, out_idx, out_d2,
                         a.out_flags ? a.out_flags + m : nullptr, extra);
 }
 
@@ -1478,20 +1508,12 @@ __global__ __launch_bounds__(256) void knn_scan(SelArgs a, int keep_extra, int32
         const int64_t r_lo = tl ? (int64_t)tl[rg] * KT : a.key_lo;
         const int64_t r_hi = tl ? min<int64_t>(r_lo + KT, nl) : nl;
         for (int64_t j0 = r_lo + w; j0 < r_hi; j0 += 16) {
-            float dj[4];
+            // four keys per pass (a key past the range repeats j0; its sum is dropped)
+            const float* xr[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int64_t j = j0 + 4 * u;
-                float acc = 0.f;
-                if (j < r_hi) {
-                    const float* xj = a.X + j * a.ld;
-                    for (int d = l; d < a.D; d += WAVE) {
-                        float tt = xq[d] - xj[d];
-                        acc = fmaf(tt, tt, acc);
-                    }
-                }
-                dj[u] = wave_sum(acc);
-            }
+            for (int u = 0; u < 4; ++u) xr[u] = a.X + (j0 + 4 * u < r_hi ? j0 + 4 * u : j0) * a.ld;
+            float dj[4];
+            direct_group<4>(xq, xr, a.D, dj);
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int64_t j = j0 + 4 * u;
