@@ -31,6 +31,12 @@ namespace atsne {
 
 constexpr int SYM_BLOCK = 1024;  // sorted entries per sym_heads / sym_emit workgroup (256 threads x 4)
 constexpr uint64_t SYM_NONE = ~0ull;  // sentinel key: (SYM_NONE >> 1) equals no real (row, column) pair
+// Radix passes at every size above one block's worth: rocPRIM's default
+// switches to a merge sort below 2^20 items, which is slower here (18 merge
+// launches for the 3.6e5 pairs of N = 2000, k = 90: the whole
+// symmetrisation took 0.27 ms that way, 0.125 ms with radix passes).
+using SymSortConfig = rocprim::radix_sort_config<rocprim::default_config, rocprim::default_config,
+                                                 rocprim::default_config, 0>;
 
 // Row extent of the conditional input: CSR (in_ptr) or fixed k.
 struct RowsIn {
@@ -200,7 +206,7 @@ static void sym_plan(int64_t N, int64_t nnz_in, SymPlan& p) {
     p.sort_bytes = 0;
     rocprim::double_buffer<uint64_t> kb(nullptr, nullptr);
     rocprim::double_buffer<float> vb(nullptr, nullptr);
-    (void)rocprim::radix_sort_pairs(nullptr, p.sort_bytes, kb, vb, (size_t)std::max<int64_t>(p.n2, 1), 0,
+    (void)rocprim::radix_sort_pairs<SymSortConfig>(nullptr, p.sort_bytes, kb, vb, (size_t)std::max<int64_t>(p.n2, 1), 0,
                                     (unsigned)(2 * p.b + 1));
     p.sort_bytes = std::max<size_t>(p.sort_bytes, 1);
     const int64_t n2 = std::max<int64_t>(p.n2, 1);
@@ -239,7 +245,7 @@ static atsne_status sym_run(const SymPlan& p, RowsIn rin, const int32_t* in_col,
         rocprim::double_buffer<uint64_t> kb(k0, k1);
         rocprim::double_buffer<float> vb(v0, v1);
         size_t sort_bytes = p.sort_bytes;
-        ATSNE_HIP(rocprim::radix_sort_pairs(sort_tmp, sort_bytes, kb, vb, (size_t)p.n2, 0, (unsigned)(2 * p.b + 1),
+        ATSNE_HIP(rocprim::radix_sort_pairs<SymSortConfig>(sort_tmp, sort_bytes, kb, vb, (size_t)p.n2, 0, (unsigned)(2 * p.b + 1),
                                             st));
         const uint64_t* K = kb.current();
         const float* V = vb.current();
