@@ -35,6 +35,7 @@ def parse():
     ap.add_argument("--no-bf16", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-fp8", action="store_true", help="skip the FP8 precision-at-scale leg (N = 10^6)")
     ap.add_argument("--path-only", action="store_true",
                     help="only the FP32 and BF16 steps (no approximate, attractive, ordering, serving legs): the "
                          "command the kernel-trace profile runs")
@@ -178,6 +179,42 @@ def max_dp_same_rows(torch, rb, r):
     if not bool(same.any()):
         return None
     return float((rb["P"][same] - r["P"][same]).abs().max().item())
+
+
+def fp8_scale_leg(A, torch, datagen, steps=2, warmup=1, sample=256, seed=13):
+    """Precision at scale: N = 10^6, D = 128 anisotropic mixture, mu = 50, k = 150, FP8 e4m3 contraction with
+    per-row scales and an FP32 re-rank of 2k = 300 candidates.  Whole-path points/s, the tile against the FP8
+    matrix-core peak, and recall / max |dP| on a seeded sample of rows against the exact FP32 path (which the
+    parity tests hold to the FP64 oracle)."""
+    X = datagen.mixture_anisotropic()
+    N, D = X.shape
+    mu, k = 50.0, 150
+    Xt = torch.from_numpy(X).cuda()
+    del X
+    r = run_path(A, torch, Xt, mu, k, "fp8", steps, warmup)
+    value = N * steps / r["wall"]
+    t_ms, t_n = r["stages"]["knn_tile"]
+    t_avg = t_ms / max(t_n, 1) * 1e-3
+    ach = 2.0 * N * N * D * steps / max(t_n, 1) / t_avg / 1e12
+    rows = np.sort(np.random.default_rng(seed).choice(N, size=sample, replace=False)).astype(np.int32)
+    q = torch.from_numpy(rows).cuda()
+    ie, de, fe = A.knn(Xt, k, prec="fp32", query_ids=q)
+    Pe, _, _, _ = A.calibrate_p(de, mu, flags=fe)
+    sub = {"idx": r["idx"][q.long()], "P": r["P"][q.long()]}
+    out = {
+        "workload": "aniso50_N1000000_D128_mu50_k150", "k_cand": 2 * k, "value": round(value, 1),
+        "ms_per_step": round(1e3 * r["wall"] / steps, 3),
+        "stages_ms": {kname: round(v[0] / steps, 3) for kname, v in r["stages"].items()},
+        "roofline": {"bound": "mfma", "kernel": "knn_tile", "achieved": round(ach, 2), "peak": PEAK["fp8"],
+                     "unit": "TFLOP/s", "frac": round(ach / PEAK["fp8"], 4), "traffic": None,
+                     "algorithmic": "2*N*D FLOP per query point x N queries per step, N=%d, D=%d" % (N, D)},
+        "sample_rows": sample,
+        "recall_vs_exact_sample": round(precision_eq9(torch, sub["idx"], ie), 6),
+        "max_abs_dP_vs_exact_same_rows": max_dp_same_rows(torch, sub, {"idx": ie, "P": Pe}),
+    }
+    del r, Xt
+    torch.cuda.empty_cache()
+    return out
 
 
 def approx_leg(A, torch, Xt, mu, k, exact_idx, exact_value, rho=0.9, C=256, iters=8, steps=5, seed=11):
@@ -460,6 +497,10 @@ def main():
         log("precision-controlled path (rho = 0.9) ...")
         line["approx_rho"] = approx_leg(A, torch, Xt, mu, k, r["idx"], value)
         log("approx: %s" % line["approx_rho"])
+    if a.workload == "imagelike" and not a.no_fp8:
+        log("precision at scale: FP8, N = 10^6 ...")
+        line["fp8_scale"] = fp8_scale_leg(A, torch, datagen)
+        log("fp8: %s" % line["fp8_scale"])
     log("attractive forces over the step's P ...")
     line["attractive"] = attractive_leg(A, torch, r["rp"], r["col"], r["val"])
     log("attractive: %.4f ms/launch, %.0f GB/s" % (line["attractive"]["avg_launch_ms"],
