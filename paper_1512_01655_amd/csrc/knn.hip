@@ -1791,6 +1791,14 @@ static int stream_splits(int MB, int T, int P) {
     return S;
 }
 
+// Keys a slot holds: k' kept plus a tile's appends plus slack, and at least
+// what make_room's register path covers (WAVE * MR_KEYS): the slack sets how
+// often a slot is cut back, and each cut waits one memory round trip for
+// the slot's keys, so the register path's full size is used.
+static int slot_cap(int kc_max) {
+    return std::max(WAVE * MR_KEYS, (int)align_up((size_t)(kc_max + KT + std::max(kc_max, 128)), 64));
+}
+
 SearchPlan plan_search(int prec, int64_t M, int64_t key_lo, int64_t key_hi, int k_max, int kc_max, int s_max,
                        bool allow_small, bool stream) {
     SearchPlan p;
@@ -1811,7 +1819,7 @@ SearchPlan plan_search(int prec, int64_t M, int64_t key_lo, int64_t key_hi, int 
     p.tile_lo = (int)(key_lo / p.kt);
     p.tile_hi = (int)ceil_div(key_hi, p.kt);
     const int total_tiles = std::max(1, p.tile_hi - p.tile_lo);
-    p.cap = (int)align_up((size_t)(kc_max + KT + std::max(kc_max, 128)), 64);
+    p.cap = slot_cap(kc_max);
     p.MB = (int)ceil_div(std::max<int64_t>(M, 1), p.qb);
     int S = pick_splits(p.MB, total_tiles, device_cu_count());
     if (s_max > 0) S = std::min(S, s_max);
@@ -1848,7 +1856,7 @@ SearchPlan plan_list_search(int64_t M, int64_t n_blocks, int k_max, int kc_max, 
     p.M = M;
     p.k_max = k_max;
     p.kc_max = kc_max;
-    p.cap = (int)align_up((size_t)(kc_max + KT + std::max(kc_max, 128)), 64);
+    p.cap = slot_cap(kc_max);
     p.MB = (int)std::max<int64_t>(n_blocks, 1);
     p.S = std::max(1, S);
     p.tiles_per_split = 1;
