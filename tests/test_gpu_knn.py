@@ -52,6 +52,24 @@ def test_knn_config1_full(A, ora, prec):
 
 
 @pytest.mark.parametrize("prec", EXACT)
+def test_knn_balanced_schedule_ragged(A, ora, prec):
+    # 24 x 24 (query block, key tile) units of 256 rows, more than two per CU:
+    # the balanced schedule, whose workgroups cross query blocks (segments run
+    # by first tile), with a ragged last block and D off the chunk size
+    X = datagen.mixture_isotropic(n=6001, d=37)
+    _compare(A, ora, X, 90, prec=prec)
+
+
+def test_knn_balanced_schedule_ragged_bf16(A, ora):
+    X = datagen.mixture_isotropic(n=6001, d=37)
+    g_idx, g_d2, g_fl = run_knn(A, X, 90, "bf16")
+    o_idx, o_d2, o_nx = ora.knn(X, 90)
+    rec = O.recall(g_idx, o_idx)
+    say("    bf16 recall %.6f" % rec)
+    assert rec >= 0.999
+
+
+@pytest.mark.parametrize("prec", EXACT)
 def test_knn_config1_kcand_equals_k(A, ora, prec):
     # no candidate margin: the certificate must route uncertain rows to the exact scan
     X = datagen.mixture_isotropic()
