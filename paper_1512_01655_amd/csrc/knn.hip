@@ -888,9 +888,19 @@ __global__ __launch_bounds__((TileGeom<P, SMALL>::THREADS)) __attribute__((amdgp
             if (n_me) {
                 // the slot pointer is formed here, not held across the chunk loop
                 uint64_t* dst = a.slots + ((size_t)mq * a.S + split) * (size_t)a.cap + count + ((l >> 5) ? n_other : 0);
+                if (mask == 0xffffu && (reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
+                    // every value passes (a slot's first tiles): two keys per
+                    // 16-byte store, half the store instructions
 #pragma unroll
-                for (int v = 0; v < 16; ++v) {
-                    if (mask & (1u << v)) *dst++ = pack_key(dv[v], kb + 8 * (v >> 2) + (v & 3));
+                    for (int v = 0; v < 16; v += 2)
+                        *reinterpret_cast<ulonglong2*>(dst + v) =
+                            make_ulonglong2(pack_key(dv[v], kb + 8 * (v >> 2) + (v & 3)),
+                                            pack_key(dv[v + 1], kb + 8 * ((v + 1) >> 2) + ((v + 1) & 3)));
+                } else {
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) {
+                        if (mask & (1u << v)) *dst++ = pack_key(dv[v], kb + 8 * (v >> 2) + (v & 3));
+                    }
                 }
             }
             count += n_me + n_other;
