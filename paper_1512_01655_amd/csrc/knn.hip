@@ -760,7 +760,9 @@ __global__ __launch_bounds__((TileGeom<P, SMALL>::THREADS)) __attribute__((amdgp
                 const float nq = a.norms[self];
                 const float nmax = nl > 0 ? a.pmax[nl - 1] : 0.0f;
                 const float dmax = a.tau0[mq * a.tau0_stride];
-                tau = dmax > -INFINITY ? dmax - nq + fp32_contraction_bound(a.Dp, nq, nmax, dmax) * 2.0f + 1e-30f
+                const float E = P == ATSNE_PREC_FP32X3 ? x3_contraction_bound(a.Dp, nq, nmax, dmax)
+                                                       : fp32_contraction_bound(a.Dp, nq, nmax, dmax);
+                tau = dmax > -INFINITY ? dmax - nq + E * 2.0f + 1e-30f
                                        : -INFINITY;  // a row with no neighbour left takes none
             }
         }
@@ -1962,17 +1964,24 @@ static atsne_status launch_tile(const Corpus& c, const Batch& b, const SearchPla
                       "the small geometry serves the plain search only");
         if constexpr (P != ATSNE_PREC_FP8_E4M3)
             knn_tile<P, TILE_PLAIN, true><<<grid, dim3(TileGeom<P, true>::THREADS), 0, st>>>(t);
-    } else if constexpr (P == ATSNE_PREC_FP32) {
+    } else if constexpr (P == ATSNE_PREC_FP32 || P == ATSNE_PREC_FP32X3) {
+        // the exact contractions: deletion stamps for the server's corpus;
+        // tile lists (the approximate search) on the FP32 corpus only
         const dim3 block(TileGeom<P>::THREADS);
         ATSNE_REQUIRE(!(c.death && b.blk_q), ATSNE_E_UNSUPPORTED, "tile lists with deletion stamps");
-        if (b.blk_q)
-            knn_tile<P, TILE_LIST, false><<<grid, block, 0, st>>>(t);
-        else if (c.death)
-            knn_tile<P, TILE_VIS, false><<<grid, block, 0, st>>>(t);
-        else
-            knn_tile<P, TILE_PLAIN, false><<<grid, block, 0, st>>>(t);
+        ATSNE_REQUIRE(!b.blk_q || P == ATSNE_PREC_FP32, ATSNE_E_UNSUPPORTED, "tile lists need the FP32 corpus");
+        if constexpr (P == ATSNE_PREC_FP32) {
+            if (b.blk_q) knn_tile<P, TILE_LIST, false><<<grid, block, 0, st>>>(t);
+        }
+        if (!b.blk_q) {
+            if (c.death)
+                knn_tile<P, TILE_VIS, false><<<grid, block, 0, st>>>(t);
+            else
+                knn_tile<P, TILE_PLAIN, false><<<grid, block, 0, st>>>(t);
+        }
     } else {
-        ATSNE_REQUIRE(!c.death && !b.blk_q, ATSNE_E_UNSUPPORTED, "deletion stamps and tile lists need the FP32 corpus");
+        ATSNE_REQUIRE(!c.death && !b.blk_q, ATSNE_E_UNSUPPORTED,
+                      "deletion stamps and tile lists need an exact contraction's corpus");
         knn_tile<P, TILE_PLAIN, false><<<grid, dim3(TileGeom<P>::THREADS), 0, st>>>(t);
     }
     ATSNE_LAUNCH_CHECK();
@@ -2071,7 +2080,8 @@ atsne_status knn_reverse(const Corpus& c, const Batch& b, const SearchPlan& p, i
                          uint8_t* res_flags, int64_t res_stride, int32_t* changed, int32_t* n_changed, void* ws,
                          hipStream_t st) {
     if (b.M == 0) return ATSNE_OK;
-    ATSNE_REQUIRE(c.prec == ATSNE_PREC_FP32, ATSNE_E_UNSUPPORTED, "reverse merge needs the FP32 corpus");
+    ATSNE_REQUIRE(c.prec == ATSNE_PREC_FP32 || c.prec == ATSNE_PREC_FP32X3, ATSNE_E_UNSUPPORTED,
+                  "reverse merge needs an exact contraction (FP32 or FP32X3 corpus)");
     ATSNE_REQUIRE(b.tau0 && b.M <= p.M && b.kc <= p.kc_max, ATSNE_E_INVALID_ARG, "bad reverse batch");
     const SearchWs w = carve(p, ws);
     ATSNE_TRY(launch_tile_any(c, b, p, w, st));

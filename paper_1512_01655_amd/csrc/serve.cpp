@@ -22,7 +22,7 @@
 // reserved before it, minus the rows deleted by earlier commits: a deleted
 // row keeps its storage and carries the index of the deleting commit), every
 // row's arithmetic is independent of the rows it shares a launch with, and
-// the FP32 error bound uses the prefix maximum of the norms, so a request's
+// the contraction's error bound uses the prefix maximum of the norms, so a request's
 // result is bitwise the same alone or in any mix.
 #include <algorithm>
 #include <atomic>
@@ -41,6 +41,13 @@ namespace atsne {
 namespace {
 
 constexpr float SERVE_MAX_PERPLEXITY = 50.0f;
+// The corpus's contraction: FP32X3 (each FP32 value as BF16 hi + lo, three
+// BF16 matrix-core products per element pair), at about twice the FP32
+// tile's speed at D = 784.  Its candidates are certified against its own
+// error bound, rows the bound cannot certify take the exact FP32 scan, and
+// the FP32 re-rank and tie test are shared, so every result equals the FP32
+// contraction's.
+constexpr int SERVE_PREC = ATSNE_PREC_FP32X3;
 
 double now_ms(std::chrono::steady_clock::time_point t0) {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -258,8 +265,8 @@ atsne_status launch_batch(atsne_server* s, BatchSlot& b, std::vector<Seg>& segs,
     }
     ATSNE_HIP(hipMemcpyAsync(b.d_desc, b.h_desc, sizeof(int32_t) * 5 * R, hipMemcpyHostToDevice, b.st));
     const int s_fit = 64;
-    SearchPlan p = plan_search(ATSNE_PREC_FP32, rows, 0, key_hi, s->kmax, s->kcmax, s_fit);
-    while (p.ws_bytes > b.ws_bytes && p.S > 1) p = plan_search(ATSNE_PREC_FP32, rows, 0, key_hi, s->kmax, s->kcmax, p.S - 1);
+    SearchPlan p = plan_search(SERVE_PREC, rows, 0, key_hi, s->kmax, s->kcmax, s_fit);
+    while (p.ws_bytes > b.ws_bytes && p.S > 1) p = plan_search(SERVE_PREC, rows, 0, key_hi, s->kmax, s->kcmax, p.S - 1);
     ATSNE_REQUIRE(p.ws_bytes <= b.ws_bytes, ATSNE_E_NOMEM, "batch workspace too small");
     Batch bt;
     bt.M = rows;
@@ -325,8 +332,8 @@ atsne_status commit_insert(atsne_server* s, Request& r) {
     ATSNE_HIP(hipMemsetAsync(r.n_changed_dev, 0, sizeof(int32_t), st));
     if (r0 > 0) {
         ATSNE_TRY(serve_farthest(s->res_idx, s->res_d2, K, r0, s->res_dmax, st));
-        SearchPlan p = plan_search(ATSNE_PREC_FP32, r0, r0, r0 + B, K, K);
-        while (p.ws_bytes > s->rev_ws_bytes && p.S > 1) p = plan_search(ATSNE_PREC_FP32, r0, r0, r0 + B, K, K, p.S - 1);
+        SearchPlan p = plan_search(SERVE_PREC, r0, r0, r0 + B, K, K);
+        while (p.ws_bytes > s->rev_ws_bytes && p.S > 1) p = plan_search(SERVE_PREC, r0, r0, r0 + B, K, K, p.S - 1);
         ATSNE_REQUIRE(p.ws_bytes <= s->rev_ws_bytes, ATSNE_E_NOMEM, "reverse workspace too small");
         Batch bt;
         bt.M = r0;
@@ -550,8 +557,8 @@ extern "C" atsne_status atsne_serve_create(const atsne_serve_config* cfg, const 
     const int64_t cap = ceil_div(s->cap_rows, KNN_KT) * KNN_KT;
     atsne_status st;
     if ((st = alloc_dev((void**)&s->X, sizeof(float) * cap * D)) != ATSNE_OK) return fail(st);
-    if ((st = alloc_dev(&s->corpus_mem, corpus_bytes(ATSNE_PREC_FP32, cap, D))) != ATSNE_OK) return fail(st);
-    corpus_bind(s->corpus, ATSNE_PREC_FP32, s->X, D, D, cap, s->corpus_mem);
+    if ((st = alloc_dev(&s->corpus_mem, corpus_bytes(SERVE_PREC, cap, D))) != ATSNE_OK) return fail(st);
+    corpus_bind(s->corpus, SERVE_PREC, s->X, D, D, cap, s->corpus_mem);
     {
         Arena a;
         a.take<int32_t>(cap * K0);
@@ -584,7 +591,7 @@ extern "C" atsne_status atsne_serve_create(const atsne_serve_config* cfg, const 
     const int64_t R = s->max_batch_rows;
     {
         // batch workspace: enough for the largest batch with a few splits
-        SearchPlan p = plan_search(ATSNE_PREC_FP32, R, 0, cap, s->kmax, s->kcmax, 4);
+        SearchPlan p = plan_search(SERVE_PREC, R, 0, cap, s->kmax, s->kcmax, 4);
         for (auto& b : s->slot) {
             b.ws_bytes = p.ws_bytes;
             if ((st = alloc_dev(&b.ws, b.ws_bytes)) != ATSNE_OK) return fail(st);
@@ -599,7 +606,7 @@ extern "C" atsne_status atsne_serve_create(const atsne_serve_config* cfg, const 
                 return fail(ATSNE_E_HIP);
             }
         }
-        SearchPlan rp = plan_search(ATSNE_PREC_FP32, cap, 0, 4096 + KNN_KT, K0, K0, 1);
+        SearchPlan rp = plan_search(SERVE_PREC, cap, 0, 4096 + KNN_KT, K0, K0, 1);
         s->rev_ws_bytes = rp.ws_bytes;
         if ((st = alloc_dev(&s->rev_ws, s->rev_ws_bytes)) != ATSNE_OK) return fail(st);
     }
@@ -616,7 +623,7 @@ extern "C" atsne_status atsne_serve_create(const atsne_serve_config* cfg, const 
     if ((st = serve_fill_death(s->death, cap, cs)) != ATSNE_OK) return fail(st);
     if ((st = corpus_prep(s->corpus, 0, cap, N, cs)) != ATSNE_OK) return fail(st);
     {
-        SearchPlan p = plan_search(ATSNE_PREC_FP32, std::min<int64_t>(N, 65536), 0, N, K0, s->kc0);
+        SearchPlan p = plan_search(SERVE_PREC, std::min<int64_t>(N, 65536), 0, N, K0, s->kc0);
         void* ws = nullptr;
         if ((st = alloc_dev(&ws, p.ws_bytes)) != ATSNE_OK) return fail(st);
         for (int64_t m0 = 0; m0 < N && st == ATSNE_OK; m0 += p.M) {
