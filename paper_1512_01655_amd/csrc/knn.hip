@@ -890,9 +890,10 @@ __global__ __launch_bounds__((TileGeom<P, SMALL>::THREADS)) __attribute__((amdgp
             if (n_me) {
                 // the slot pointer is formed here, not held across the chunk loop
                 uint64_t* dst = a.slots + ((size_t)mq * a.S + split) * (size_t)a.cap + count + ((l >> 5) ? n_other : 0);
-                if (mask == 0xffffu && (reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
+                if (MODE == TILE_PLAIN && mask == 0xffffu && (reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
                     // every value passes (a slot's first tiles): two keys per
-                    // 16-byte store, half the store instructions
+                    // 16-byte store, half the store instructions (plain mode
+                    // only: with stamps or tile lists it doubles the spills)
 #pragma unroll
                     for (int v = 0; v < 16; v += 2)
                         *reinterpret_cast<ulonglong2*>(dst + v) =
