@@ -50,6 +50,11 @@ namespace {
 
 constexpr int IVF_TILE = KNN_KT;
 constexpr int IVF_MAX_C = 1024;  // the probe order is a (C - 1)-NN search among centroids
+// The sorted corpus's contraction: FP32X3 (BF16 hi + lo, three BF16
+// matrix-core products per element pair), whose candidate rows and exact
+// re-rank equal the FP32 contraction's at about twice the tile speed.  The
+// centroid searches of the build stay FP32 (they are tiny).
+constexpr int IVF_PREC = ATSNE_PREC_FP32X3;
 
 __global__ __launch_bounds__(256) void ivf_gather(const float* __restrict__ src, const int32_t* __restrict__ ids,
                                                   int64_t n, int32_t D, float* __restrict__ dst) {
@@ -429,11 +434,11 @@ extern "C" atsne_status atsne_ivf_build(const float* X, int64_t N, int32_t D, in
     }
     // the sorted corpus the searches run on
     if ((s_ = alloc((void**)&ix->Xperm, sizeof(float) * cap * D)) != ATSNE_OK) return fail(s_);
-    if ((s_ = alloc(&ix->cmem, corpus_bytes(ATSNE_PREC_FP32, cap, D))) != ATSNE_OK) return fail(s_);
+    if ((s_ = alloc(&ix->cmem, corpus_bytes(IVF_PREC, cap, D))) != ATSNE_OK) return fail(s_);
     if (hipMemsetAsync(ix->Xperm + N * D, 0, sizeof(float) * (cap - N) * D, st) != hipSuccess)
         return fail(ATSNE_E_HIP);
     ivf_gather<<<(unsigned)N, 256, 0, st>>>(pts, ix->perm, N, D, ix->Xperm);
-    corpus_bind(ix->corpus, ATSNE_PREC_FP32, ix->Xperm, D, D, cap, ix->cmem);
+    corpus_bind(ix->corpus, IVF_PREC, ix->Xperm, D, D, cap, ix->cmem);
     if ((s_ = corpus_prep(ix->corpus, 0, cap, N, st)) != ATSNE_OK) return fail(s_);
     if (hipStreamSynchronize(st) != hipSuccess) {
         set_error("build failed");
@@ -522,7 +527,7 @@ extern "C" atsne_status atsne_ivf_fit(atsne_ivf* ix, int32_t k, float rho, const
     // exact neighbours of the sample over the whole corpus
     {
         const int kc = (int)std::min<int64_t>(k + std::max(32, k / 2), ix->N - 1);
-        SearchPlan p = plan_search(ATSNE_PREC_FP32, M, 0, ix->N, k, kc);
+        SearchPlan p = plan_search(IVF_PREC, M, 0, ix->N, k, kc);
         ATSNE_TRY(ews.get(p.ws_bytes));
         Batch b;
         b.M = M;

@@ -1966,20 +1966,16 @@ static atsne_status launch_tile(const Corpus& c, const Batch& b, const SearchPla
         if constexpr (P != ATSNE_PREC_FP8_E4M3)
             knn_tile<P, TILE_PLAIN, true><<<grid, dim3(TileGeom<P, true>::THREADS), 0, st>>>(t);
     } else if constexpr (P == ATSNE_PREC_FP32 || P == ATSNE_PREC_FP32X3) {
-        // the exact contractions: deletion stamps for the server's corpus;
-        // tile lists (the approximate search) on the FP32 corpus only
+        // the exact contractions: deletion stamps (the server's corpus) and
+        // tile lists (the approximate search's corpus)
         const dim3 block(TileGeom<P>::THREADS);
         ATSNE_REQUIRE(!(c.death && b.blk_q), ATSNE_E_UNSUPPORTED, "tile lists with deletion stamps");
-        ATSNE_REQUIRE(!b.blk_q || P == ATSNE_PREC_FP32, ATSNE_E_UNSUPPORTED, "tile lists need the FP32 corpus");
-        if constexpr (P == ATSNE_PREC_FP32) {
-            if (b.blk_q) knn_tile<P, TILE_LIST, false><<<grid, block, 0, st>>>(t);
-        }
-        if (!b.blk_q) {
-            if (c.death)
-                knn_tile<P, TILE_VIS, false><<<grid, block, 0, st>>>(t);
-            else
-                knn_tile<P, TILE_PLAIN, false><<<grid, block, 0, st>>>(t);
-        }
+        if (b.blk_q)
+            knn_tile<P, TILE_LIST, false><<<grid, block, 0, st>>>(t);
+        else if (c.death)
+            knn_tile<P, TILE_VIS, false><<<grid, block, 0, st>>>(t);
+        else
+            knn_tile<P, TILE_PLAIN, false><<<grid, block, 0, st>>>(t);
     } else {
         ATSNE_REQUIRE(!c.death && !b.blk_q, ATSNE_E_UNSUPPORTED,
                       "deletion stamps and tile lists need an exact contraction's corpus");
