@@ -215,7 +215,8 @@ atsne_status atsne_attractive_forces(const int64_t* row_ptr, const int32_t* col,
  *          clusters (further probe clusters are added until the tiles hold at
  *          least k + 1 rows); the result is the exact FP32 kNN over those
  *          candidates (same re-rank, tie rule and FP64 near-tie handling as
- *          atsne_knn).  n_probe >= n_clusters gives the exact kNN.
+ *          atsne_knn; the contraction is FP32X3, whose results equal
+ *          FP32's).  n_probe >= n_clusters gives the exact kNN.
  *   fit    the smallest n_probe whose precision (Eq. 9, against the exact
  *          kNN) over all points of the sample clusters reaches rho; precision
  *          never decreases with n_probe, so it is found by bisection.
@@ -347,7 +348,9 @@ typedef struct atsne_serve_stats {
 
 /* Create a server over a copy of corpus [N x D] (device or host FP32, row
  * stride D), with its exact kNN at perplexity mu (k = floor(3 mu)) computed
- * at creation.  *out receives the handle. */
+ * at creation.  Every search of the server runs the FP32X3 contraction; its
+ * results equal those of atsne_knn with ATSNE_PREC_FP32.  *out receives the
+ * handle. */
 atsne_status atsne_serve_create(const atsne_serve_config* cfg, const float* corpus, int64_t N, int32_t D,
                                 float perplexity, atsne_server** out);
 /* Queue an insert of B points X_new [B x D] (device FP32).  Returns at once
