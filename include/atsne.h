@@ -91,7 +91,9 @@ atsne_status atsne_profile_read(const char* name, double* total_ms, int64_t* cou
 
 /* Scratch bytes needed by atsne_knn / atsne_knn_subset for a corpus of N rows
  * of dimension D, M query rows, k neighbours and k_cand candidates
- * (0 = the precision's default). */
+ * (0 = the precision's default), on the current device: the candidate slots
+ * take up to a sixteenth of its memory (between 2 and 16 GiB), and query
+ * rows beyond what that holds are searched in batches. */
 atsne_status atsne_knn_workspace_size(int64_t N, int64_t M, int32_t D, atsne_precision prec, int32_t k,
                                       int32_t k_cand, size_t* bytes);
 

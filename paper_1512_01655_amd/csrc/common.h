@@ -99,6 +99,8 @@ struct Scratch {
 
 // Number of compute units of the current device (cached per device).
 int device_cu_count();
+// Global memory of the current device in bytes (0 when there is no device).
+size_t device_hbm_bytes();
 
 // Optional per-kernel timing: brackets a launch with HIP events on its
 // stream while profiling is enabled (atsne_profile_enable).

@@ -2125,9 +2125,13 @@ static atsne_status make_plan(int64_t N, int64_t M, int32_t D, int prec, int k, 
     p.M = M;
     p.D = D;
     p.b_corpus = corpus_bytes(prec, N, D);
-    // Keep the candidate slots within ~2 GiB: fewer key splits first, then
-    // batches of query rows.
-    const size_t slot_budget = (size_t)2 << 30;
+    // Keep the candidate slots within a sixteenth of the device's memory,
+    // between 2 and 16 GiB (16 GiB on a 288 GB MI355X): fewer key splits
+    // first, then batches of query rows.  Each batch re-streams the whole
+    // corpus, so the larger budget pays at large N (N = 10^6, FP8: four
+    // launches in 2 GiB, one in 16 GiB, 9% faster).
+    const size_t slot_budget =
+        std::min<size_t>((size_t)16 << 30, std::max<size_t>((size_t)2 << 30, device_hbm_bytes() / 16));
     const int64_t Mq = std::max<int64_t>(M, 1);
     SearchPlan full = plan_search(prec, Mq, 0, N, k, kc, 0, true, true);
     if (full.ws_bytes > slot_budget && full.S > 1) {

@@ -19,6 +19,21 @@ void set_error(const char* fmt, ...) {
 
 void clear_error() { g_err[0] = '\0'; }
 
+size_t device_hbm_bytes() {
+    static std::mutex mu;
+    static std::vector<size_t> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    std::lock_guard<std::mutex> lk(mu);
+    if (dev >= (int)cache.size()) cache.resize(dev + 1, 0);
+    if (cache[dev] == 0) {
+        size_t bytes = 0;
+        if (hipDeviceTotalMem(&bytes, dev) != hipSuccess) bytes = 0;
+        cache[dev] = bytes;
+    }
+    return cache[dev];
+}
+
 int device_cu_count() {
     static std::mutex mu;
     static std::vector<int> cache;
