@@ -385,7 +385,7 @@ def main():
     a = parse()
     if a.gpus != 1:
         print("bench.py: this build measures one GPU; --gpus %d is not supported (the path would shard by "
-              "query rows, see DESIGN.md)" % a.gpus, file=sys.stderr)
+              "query rows)" % a.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
 
