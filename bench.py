@@ -384,7 +384,7 @@ def cpu_baseline(X, mu, k, target_s):
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py: this build measures one GPU; --gpus %d is not supported (the path would shard by "
+        print("bench.py measures one GPU; --gpus %d is not supported (the path would shard by "
               "query rows)" % a.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
