@@ -116,6 +116,25 @@ def test_symmetrize_hand_example(A):
     assert val.tolist() == [5 / 32, 1 / 32, 1 / 64, 5 / 32, 7 / 64, 1 / 32, 7 / 64, 3 / 16, 1 / 64, 3 / 16]
 
 
+def test_symmetrize_two_points(A):
+    rp, col, val = _sym(A, np.array([[1], [0]], np.int32), np.array([[1.0], [1.0]]))
+    assert rp.tolist() == [0, 1, 2] and col.tolist() == [1, 0]
+    assert val.tolist() == [0.5, 0.5]
+
+
+def test_symmetrize_complete_graph(A, ora):
+    # k = N - 1: every pair is both an own and a mirrored entry, so the union
+    # is the complete graph and nnz = N (N - 1)
+    rng = np.random.default_rng(15)
+    N = 50
+    idx = np.array([rng.permutation(np.delete(np.arange(N), i)) for i in range(N)], np.int32)
+    P = rng.dirichlet(np.ones(N - 1), size=N)
+    Pf = P.astype(np.float32)
+    g = _sym(A, idx, Pf)
+    assert g[0][-1] == N * (N - 1)
+    _check_sym_equal(N, g, ora.symmetrize(idx, Pf.astype(np.float64)))
+
+
 def test_symmetrize_on_oracle_rows_config1(A, ora):
     X = datagen.mixture_isotropic()
     idx, d2, _ = ora.knn(X, 90)
