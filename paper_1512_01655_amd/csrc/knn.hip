@@ -1508,8 +1508,11 @@ __global__ __launch_bounds__(256) void knn_scan(SelArgs a, int keep_extra, int32
         int32_t* out_idx = a.out_idx + m * a.out_stride;
         float* out_d2 = a.out_d2 + m * a.out_stride;
         const float* xq = a.X + q * a.ld;
-        // The current k-th exact distance bounds the true k-th from above.
-        float tau = out_d2[k - 1];
+        // The current k-th exact distance bounds the true k-th from above;
+        // widened by the near-tie band, so the keys just past the k-th (which
+        // the near-tie test and the FP64 re-rank look at) stay candidates and
+        // the row ends exactly as a certified row would.
+        float tau = out_d2[k - 1] * (1.0f + 4.0f * TIE_REL);
         bool strict = false;
         int cnt = 0;
         // key ranges: the row's tile list, or [key_lo, nl); ascending either way

@@ -77,6 +77,23 @@ def test_knn_config1_kcand_equals_k(A, ora, prec):
 
 
 @pytest.mark.parametrize("prec", EXACT)
+def test_knn_exact_scan_equals_certified(A, prec):
+    # k_cand = k leaves no candidate margin, so most rows are redone by the
+    # exact scan; the scan keeps the near-tie band past the k-th, so every
+    # row (neighbours, distances, FP64 re-rank) ends bit for bit as with the
+    # default margin, where rows are certified
+    X = datagen.mixture_isotropic()
+    a_idx, a_d2, a_fl = run_knn(A, X, 90, prec, 0)
+    b_idx, b_d2, b_fl = run_knn(A, X, 90, prec, 90)
+    n_scan = int(((b_fl & 8) > 0).sum())
+    say("    exact-scan rows %d (margin 0) vs %d (default); fp64 rows %d / %d" % (
+        n_scan, int(((a_fl & 8) > 0).sum()), int((a_fl & 1).sum()), int((b_fl & 1).sum())))
+    assert n_scan > 100
+    assert np.array_equal(a_idx, b_idx) and np.array_equal(a_d2, b_d2)
+    assert np.array_equal(a_fl & 1, b_fl & 1)
+
+
+@pytest.mark.parametrize("prec", EXACT)
 def test_knn_integer_ties_exact(A, ora, prec):
     # small integers: every distance is exact in FP32, so the (d, j) ranking,
     # ties included, must match bit for bit
