@@ -143,6 +143,19 @@ def test_knn_subset(A, ora, prec):
     _compare(A, ora, X, 90, prec=prec, qids=q)
 
 
+@pytest.mark.parametrize("prec", EXACT)
+def test_knn_subset_rows_equal_full_search(A, prec):
+    # a row's result does not depend on the rows searched with it: the
+    # subset search (few query blocks, small geometry, task grid) and the
+    # full search (balanced schedule) give the same rows bit for bit
+    X = datagen.mixture_isotropic(n=6001, d=37)
+    q = np.random.default_rng(16).choice(6001, size=500, replace=False).astype(np.int32)
+    f_idx, f_d2, f_fl = run_knn(A, X, 90, prec)
+    s_idx, s_d2, s_fl = run_knn(A, X, 90, prec, qids=q)
+    assert np.array_equal(s_idx, f_idx[q]) and np.array_equal(s_d2, f_d2[q])
+    assert np.array_equal(s_fl & 1, f_fl[q] & 1)
+
+
 def test_knn_errors(A):
     import torch
 
