@@ -156,6 +156,15 @@ def test_knn_subset_rows_equal_full_search(A, prec):
     assert np.array_equal(s_fl & 1, f_fl[q] & 1)
 
 
+def test_knn_fp32x3_equals_fp32_small_and_ragged(A):
+    # the two exact contractions give the same rows bit for bit on the small
+    # geometry (N = 2000) and the balanced schedule (N = 6001, D = 37)
+    for X in (datagen.mixture_isotropic(), datagen.mixture_isotropic(n=6001, d=37)):
+        a = run_knn(A, X, 90, "fp32")
+        b = run_knn(A, X, 90, "fp32x3")
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+
+
 def test_knn_errors(A):
     import torch
 
