@@ -84,6 +84,11 @@ def test_search_matches_definition(A, n_probe):
     say("    n_probe %d: candidates %.3f of N, precision %.4f, %d tie-rule rows" % (n_probe, frac, rho, ties))
     if n_probe == C:
         assert frac == 1.0 and rho == 1.0
+        # every tile probed: the exact search's rows bit for bit (the index
+        # searches a cluster-sorted copy on its own contraction)
+        x_idx, x_d2, _ = A.knn(torch.from_numpy(X).cuda(), k)
+        assert np.array_equal(idx.cpu().numpy(), x_idx.cpu().numpy())
+        assert np.array_equal(d2.cpu().numpy(), x_d2.cpu().numpy())
     ix.close()
 
 
