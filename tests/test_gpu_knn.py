@@ -143,7 +143,7 @@ def test_knn_subset(A, ora, prec):
     _compare(A, ora, X, 90, prec=prec, qids=q)
 
 
-@pytest.mark.parametrize("prec", EXACT)
+@pytest.mark.parametrize("prec", EXACT + ["bf16", "fp8"])
 def test_knn_subset_rows_equal_full_search(A, prec):
     # a row's result does not depend on the rows searched with it: the
     # subset search (few query blocks, small geometry, task grid) and the
