@@ -165,6 +165,24 @@ def test_knn_fp32x3_equals_fp32_small_and_ragged(A):
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
 
 
+@pytest.mark.parametrize("prec", EXACT + ["bf16"])
+def test_knn_strided_rows_equal_contiguous(A, prec):
+    # X as a view with row stride ld = D + 8 = 53 floats (odd, so rows start
+    # off 16-byte boundaries) gives the rows of the contiguous copy bit for bit
+    import torch
+
+    X = datagen.mixture_isotropic(n=1500, d=45)
+    big = torch.zeros((1500, 53), dtype=torch.float32, device="cuda")
+    big[:, :45] = torch.from_numpy(X).cuda()
+    view = big[:, :45]
+    assert view.stride(0) == 53
+    a = A.knn(view, 40, prec=prec)
+    b = A.knn(torch.from_numpy(X).cuda(), 40, prec=prec)
+    torch.cuda.synchronize()
+    for u, v in zip(a, b):
+        assert torch.equal(u, v)
+
+
 def test_knn_errors(A):
     import torch
 
