@@ -183,6 +183,18 @@ def test_knn_strided_rows_equal_contiguous(A, prec):
         assert torch.equal(u, v)
 
 
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_knn_all_candidates_equal_exact(A, prec):
+    # with every key a candidate (k_cand = N - 1) the low-precision
+    # contraction only orders the candidates, and the FP32 re-rank (FP64 for
+    # near ties) returns the exact path's rows bit for bit
+    X = datagen.mixture_isotropic(n=1000, d=40)
+    a_idx, a_d2, a_fl = run_knn(A, X, 30, "fp32")
+    b_idx, b_d2, b_fl = run_knn(A, X, 30, prec, kc=999)
+    assert np.array_equal(a_idx, b_idx) and np.array_equal(a_d2, b_d2)
+    assert np.array_equal(a_fl & 1, b_fl & 1)
+
+
 def test_knn_errors(A):
     import torch
 
