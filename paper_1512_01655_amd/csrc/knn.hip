@@ -7,8 +7,9 @@
 //
 // Pipeline (all on the caller's stream, no host synchronisation):
 //   knn_prep       padded copy of X in the contraction's element type
-//                  (FP32 / BF16 RNE / FP8 e4m3 with per-row absmax scales),
-//                  row norms n_i = ||x_i||^2 and the corpus max norm.
+//                  (FP32 / BF16 RNE / FP8 e4m3 with per-row absmax scales /
+//                  FP32X3: BF16 hi and lo parts of each FP32 value), row
+//                  norms n_i = ||x_i||^2 and their prefix maximum.
 //   knn_tile       S = X_q X_k^T on MFMA, d'_ij = n_j - 2 S_ij (n_i is a row
 //                  constant and irrelevant to the ranking), self and padding
 //                  masked; operands staged by direct global -> LDS loads; a
@@ -17,13 +18,16 @@
 //                  k_cand + slack keys, new threshold) whenever it fills, and
 //                  shrunk exactly to the best k_cand at the end.
 //   knn_select     per query, the best k_cand keys (d', j) over all splits,
-//                  exact FP32 direct-difference distances for them, sorted by
-//                  (d, j); rows whose k-th/(k+1)-th gap is under FP32
-//                  resolution are re-ranked in FP64.  On the FP32 path a
-//                  rigorous error bound of the contraction certifies that no
-//                  non-candidate can beat the k-th neighbour; rows it cannot
-//                  certify are queued for knn_scan.
-//   knn_scan       exact FP32 linear scan for the queued rows (rare).
+//                  exact FP32 direct-difference distances for those that can
+//                  reach the (k+1)-th place (on the exact contractions the
+//                  contraction's error bound rules the others out), sorted
+//                  by (d, j); rows whose k-th/(k+1)-th gap is under FP32
+//                  resolution are re-ranked in FP64.  On the exact
+//                  contractions (FP32, FP32X3) the same bound certifies that
+//                  no non-candidate can beat the k-th neighbour; rows it
+//                  cannot certify are queued for knn_scan.
+//   knn_scan       exact FP32 linear scan for the queued rows (rare); a
+//                  scanned row ends exactly as a certified row would.
 #include <algorithm>
 #include <cmath>
 #include <type_traits>
