@@ -135,6 +135,20 @@ def test_symmetrize_complete_graph(A, ora):
     _check_sym_equal(N, g, ora.symmetrize(idx, Pf.astype(np.float64)))
 
 
+def test_symmetrize_csr_form_equals_fixed_k(A):
+    # the same conditional rows given as fixed-k and as CSR: identical output
+    rng = np.random.default_rng(17)
+    N, k = 1200, 25
+    idx = np.array([rng.choice(np.delete(np.arange(N), i), size=k, replace=False) for i in range(N)], np.int32)
+    P = rng.dirichlet(np.ones(k), size=N).astype(np.float32)
+    a = _sym(A, idx, P)
+    ptr = torch.arange(0, N * k + 1, k, dtype=torch.int64, device="cuda")
+    rp, c, v = A.symmetrize_csr(ptr, torch.from_numpy(idx.reshape(-1)).cuda(), torch.from_numpy(P.reshape(-1)).cuda())
+    torch.cuda.synchronize()
+    assert np.array_equal(a[0], rp.cpu().numpy()) and np.array_equal(a[1], c.cpu().numpy())
+    assert np.array_equal(a[2], v.cpu().numpy())
+
+
 def test_symmetrize_on_oracle_rows_config1(A, ora):
     X = datagen.mixture_isotropic()
     idx, d2, _ = ora.knn(X, 90)

@@ -195,6 +195,16 @@ def test_knn_all_candidates_equal_exact(A, prec):
     assert np.array_equal(a_fl & 1, b_fl & 1)
 
 
+@pytest.mark.parametrize("prec", EXACT)
+def test_knn_subset_repeated_ids(A, prec):
+    # a query id listed several times gets the same row each time
+    X = datagen.mixture_isotropic()
+    q = np.array([5, 5, 17, 5, 1999, 17, 0], np.int32)
+    idx, d2, fl = run_knn(A, X, 90, prec, qids=q)
+    f_idx, f_d2, f_fl = run_knn(A, X, 90, prec)
+    assert np.array_equal(idx, f_idx[q]) and np.array_equal(d2, f_d2[q])
+
+
 def test_knn_errors(A):
     import torch
 
