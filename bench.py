@@ -206,7 +206,8 @@ def fp8_scale_leg(A, torch, datagen, steps=2, warmup=1, sample=256, seed=13):
         "ms_per_step": round(1e3 * r["wall"] / steps, 3),
         "stages_ms": {kname: round(v[0] / steps, 3) for kname, v in r["stages"].items()},
         "roofline": {"bound": "mfma", "kernel": "knn_tile", "achieved": round(ach, 2), "peak": PEAK["fp8"],
-                     "unit": "TFLOP/s", "frac": round(ach / PEAK["fp8"], 4), "traffic": None,
+                     "unit": "TFLOP/s", "frac": round(ach / PEAK["fp8"], 4),
+                     "traffic": measured_traffic("aniso", "fp8"),
                      "algorithmic": "2*N*D FLOP per query point x N queries per step, N=%d, D=%d" % (N, D)},
         "sample_rows": sample,
         "recall_vs_exact_sample": round(precision_eq9(torch, sub["idx"], ie), 6),
