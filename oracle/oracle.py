@@ -203,10 +203,46 @@ def get() -> Oracle:
     return _default
 
 
-def recall(gpu_idx: np.ndarray, ora_idx: np.ndarray) -> float:
-    """Mean over rows of |S_i intersect O_i| / K -- the precision rho of Eq. 9."""
-    M, K = ora_idx.shape
+def check_rows(rows: np.ndarray, query_ids=None, n: int | None = None) -> None:
+    """Raise ValueError unless every row is a valid neighbour list: distinct
+    ids, none equal to the row's own id (``query_ids``, when given), each in
+    [0, n) (when ``n`` is given); -1 marks an absent entry (Sec. 5.3) and may
+    only follow the listed ids."""
+    rows = np.asarray(rows)
+    if rows.ndim != 2:
+        raise ValueError("neighbour lists must be a 2-D array")
+    own = None if query_ids is None else np.asarray(query_ids).reshape(-1)
+    if own is not None and own.shape[0] != rows.shape[0]:
+        raise ValueError("one query id per row")
+    for r in range(rows.shape[0]):
+        row = [int(v) for v in rows[r]]
+        listed = [v for v in row if v != -1]
+        if row[:len(listed)] != listed:
+            raise ValueError("row %d: an absent entry (-1) before a listed id" % r)
+        if len(set(listed)) != len(listed):
+            raise ValueError("row %d lists an id twice" % r)
+        if any(v < 0 or (n is not None and v >= n) for v in listed):
+            raise ValueError("row %d lists an id outside [0, %s)" % (r, n))
+        if own is not None and int(own[r]) in listed:
+            raise ValueError("row %d lists its own id %d" % (r, int(own[r])))
+
+
+def recall(approx: np.ndarray, exact: np.ndarray, query_ids=None, n: int | None = None) -> float:
+    """The precision rho of Eq. 9: the mean over rows of |N^A_i & N_i| / |N_i|,
+    N^A_i the approximate (or low-precision) neighbour list and N_i the exact
+    one of the same row.  Both are validated first (``check_rows``): a list
+    with a repeated, self or out-of-range id raises ValueError instead of
+    being scored, and an absent entry (-1) is a miss."""
+    approx = np.asarray(approx)
+    exact = np.asarray(exact)
+    if approx.shape[0] != exact.shape[0]:
+        raise ValueError("approximate and exact lists cover different rows")
+    check_rows(approx, query_ids, n)
+    check_rows(exact, query_ids, n)
+    M, K = exact.shape
+    if M == 0:
+        return 1.0
     tot = 0
-    for a, b in zip(gpu_idx, ora_idx):
-        tot += len(np.intersect1d(a, b, assume_unique=True))
+    for a, b in zip(approx.tolist(), exact.tolist()):
+        tot += len(set(a) & set(b) - {-1})
     return tot / float(M * K)

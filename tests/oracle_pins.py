@@ -398,9 +398,40 @@ def pin_attr_exaggeration(o):
     assert np.all(F[4] == 0.0)  # an isolated point feels no attraction
 
 
+# --------------------------------------------------------------------------
+# Precision rho (Eq. 9): mean over rows of |N^A_i & N_i| / |N_i|
+# --------------------------------------------------------------------------
+
+
+def pin_recall(o, recall=None):
+    """Eq. 9 on hand-counted rows; invalid lists are refused, not scored."""
+    from oracle import oracle as O
+
+    rec = recall or O.recall
+    # rows share 2 of 3 and 3 of 3 ids: (2 + 3) / 6
+    assert rec(np.array([[1, 2, 3], [4, 5, 6]]), np.array([[3, 2, 9], [6, 5, 4]])) == 5 / 6
+    # order inside a row does not matter; identical lists score 1, disjoint 0
+    e = np.array([[7, 8, 9, 10]])
+    assert rec(e[:, ::-1], e) == 1.0
+    assert rec(np.array([[0, 1, 2, 3]]), e) == 0.0
+    # an absent entry (-1, a deleted neighbour) is a miss: 1 of 3
+    assert rec(np.array([[1, -1, -1]]), np.array([[1, 2, 3]])) == 1 / 3
+    # a repeated id must not count twice: the list is refused
+    for bad, kw in [(np.array([[1, 1, 1]]), {}),            # duplicates
+                    (np.array([[4, 2, 3]]), {"query_ids": [4]}),  # the row's own id
+                    (np.array([[1, 2, 9]]), {"n": 5}),          # outside [0, n)
+                    (np.array([[1, -1, 2]]), {})]:              # a listed id after an absent one
+        try:
+            rec(bad, np.array([[1, 2, 3]]), **kw)
+        except ValueError:
+            continue
+        raise AssertionError("recall scored an invalid list %s" % bad.tolist())
+
+
 KNN_PINS = [pin_knn_exact_rational, pin_knn_line, pin_knn_sklearn, pin_knn_metamorphic, pin_knn_subset]
 CAL_PINS = [pin_calibrate_two_level, pin_calibrate_progression, pin_calibrate_invariants,
             pin_calibrate_scaling, pin_calibrate_degenerate, pin_calibrate_brentq]
 SYM_PINS = [pin_symmetrize_hand, pin_symmetrize_dense, pin_pipeline_small]
 ATTR_PINS = [pin_attr_two_points, pin_attr_exact_rational, pin_attr_invariants, pin_attr_exaggeration]
-ALL_PINS = KNN_PINS + CAL_PINS + SYM_PINS + ATTR_PINS
+METRIC_PINS = [pin_recall]
+ALL_PINS = KNN_PINS + CAL_PINS + SYM_PINS + ATTR_PINS + METRIC_PINS
