@@ -212,13 +212,15 @@ atsne_status atsne_attractive_forces(const int64_t* row_ptr, const int32_t* col,
  *          (squared distance, index), taken again after the last update.  The
  *          corpus is sorted by (cluster, index); each cluster's probe order is
  *          itself, then the other clusters by (centroid distance, index).
- *   knn    every point's candidates are the rows of the 256-row tiles of the
- *          sorted corpus that overlap its cluster's first n_probe probe
- *          clusters (further probe clusters are added until the tiles hold at
- *          least k + 1 rows); the result is the exact FP32 kNN over those
- *          candidates (same re-rank, tie rule and FP64 near-tie handling as
- *          atsne_knn; the contraction is FP32X3, whose results equal
- *          FP32's).  n_probe >= n_clusters gives the exact kNN.
+ *   knn    every point's candidate clusters are its cluster's first n_probe
+ *          probe clusters, with further probe clusters added until their rows
+ *          number at least k + 1; the search covers the 256-row tiles of the
+ *          sorted corpus that overlap those clusters' rows (a superset of
+ *          them: the tile kernel works on whole tiles), and the result is the
+ *          exact FP32 kNN over the covered rows (same re-rank, tie rule and
+ *          FP64 near-tie handling as atsne_knn; the contraction is FP32X3,
+ *          whose results equal FP32's).  n_probe >= n_clusters gives the
+ *          exact kNN.
  *   fit    the smallest n_probe whose precision (Eq. 9, against the exact
  *          kNN) over all points of the sample clusters reaches rho; precision
  *          never decreases with n_probe, so it is found by bisection.
@@ -306,7 +308,12 @@ atsne_status atsne_order_neighbourhood(const int32_t* nbr_idx, const float* nbr_
  * Inserts and deletes are commits, applied in arrival order.  Every request
  * carries a view (`epoch`): the number of commits submitted before it.  A
  * request sees exactly the corpus those commits define, so its result does
- * not depend on what else shares the GPU. */
+ * not depend on what else shares the GPU.
+ * Latency stamps (atsne_result.t_*_ms) start at the caller's submit call.
+ * Failure: if a batched launch or a commit fails, the server stops serving:
+ * it waits for its streams to drain, completes every admitted and queued
+ * request with that status, and refuses later submissions (and snapshots)
+ * with it; results already delivered stay valid until released. */
 
 typedef struct atsne_server atsne_server;
 
@@ -314,7 +321,8 @@ typedef struct atsne_serve_config {
     size_t hbm_budget_bytes; /* cap on request scratch in flight (0 = 4 GiB) */
     int32_t max_slots;       /* max requests in flight at once (0 = 8) */
     int64_t capacity_rows;   /* corpus rows the server can grow to (0 = 2 * N) */
-    int32_t max_batch_rows;  /* rows per batched launch (0 = 16384) */
+    int32_t max_batch_rows;  /* rows per batched launch (0 = 8192); a request with more rows
+                                is split across launches */
     int32_t device;          /* HIP device ordinal (-1 = current) */
 } atsne_serve_config;
 

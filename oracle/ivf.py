@@ -15,29 +15,25 @@ and this module holds that search's definition, step by step, in FP64:
                                  permutation and each cluster's row range.
   probe_order(cent)              per cluster, all clusters by (distance
                                  between centroids, index), itself first.
-  candidate_tiles(start, probe, n_probe, K, N)
-                                 per cluster, the 256-row tiles of the sorted
-                                 corpus that overlap its first n_probe probe
+  candidate_clusters(start, probe, n_probe, K)
+                                 per cluster, its first n_probe probe
                                  clusters, extended with further probe
-                                 clusters until the tiles hold at least K + 1
-                                 rows.  A point's candidates are the rows of
-                                 its own cluster's tiles.
+                                 clusters until their rows number at least
+                                 K + 1.  A point's candidates are the rows of
+                                 its own cluster's candidate clusters.
   search(X, K, assign, C, cent, n_probe)
                                  exact kNN of every point over its candidates.
   precision(approx, exact)       Eq. 9: mean over rows of |N^A_i & N_i| / K.
 
 Parity status: pinned by ``tests/test_oracle_ivf.py`` (reduction to plain
 kNN, brute force on small inputs, scipy distances, hand examples, the k-means
-objective never increasing).
+objective never increasing, precision never falling as candidates grow).
 """
 from __future__ import annotations
 
 import numpy as np
 
 from oracle import oracle as O
-
-TILE = 256
-
 
 def sqdist(A, B):
     A = np.asarray(A, np.float64)
@@ -85,25 +81,21 @@ def probe_order(cent):
     return out
 
 
-def candidate_tiles(start, probe, n_probe, K, N):
-    C = probe.shape[0]
-    tiles = []
-    for c in range(C):
-        cover = set()
-        used = 0
+def candidate_clusters(start, probe, n_probe, K):
+    """Per cluster, the probe clusters whose rows are its points' candidates:
+    the first n_probe of its probe order, then further ones until their rows
+    number at least K + 1 (an empty cluster counts towards n_probe)."""
+    probe = np.asarray(probe)
+    out = []
+    for c in range(probe.shape[0]):
+        chosen, rows = [], 0
         for p in probe[c]:
-            if used >= n_probe and len(cover) > 0 and _rows(cover, N) >= K + 1:
+            if len(chosen) >= n_probe and rows >= K + 1:
                 break
-            used += 1
-            lo, hi = int(start[p]), int(start[p + 1])
-            if hi > lo:
-                cover.update(range(lo // TILE, (hi - 1) // TILE + 1))
-        tiles.append(sorted(cover))
-    return tiles
-
-
-def _rows(cover, N):
-    return sum(min(N, (t + 1) * TILE) - t * TILE for t in cover)
+            chosen.append(int(p))
+            rows += int(start[p + 1]) - int(start[p])
+        out.append(chosen)
+    return out
 
 
 def search(X, K, assign, C, cent, n_probe, oracle=None, probe=None, rows=None):
@@ -114,21 +106,18 @@ def search(X, K, assign, C, cent, n_probe, oracle=None, probe=None, rows=None):
     N = X.shape[0]
     assign = np.asarray(assign)
     perm, start = cluster_order(assign, C)
-    tiles = candidate_tiles(start, probe_order(cent) if probe is None else np.asarray(probe), n_probe, K, N)
+    clusters = candidate_clusters(start, probe_order(cent) if probe is None else np.asarray(probe), n_probe, K)
     rows = np.arange(N, dtype=np.int32) if rows is None else np.asarray(rows, np.int32)
     ptr = [0]
     cand = []
     for i in rows:
-        for t in tiles[assign[i]]:
-            cand.extend(perm[t * TILE:min(N, (t + 1) * TILE)].tolist())
+        for p in clusters[assign[i]]:
+            cand.extend(perm[start[p]:start[p + 1]].tolist())
         ptr.append(len(cand))
     idx, d2, nxt = ora.knn_candidates(X, K, rows, np.array(ptr), np.array(cand, np.int32))
     return idx, d2, nxt, np.diff(np.array(ptr))
 
 
 def precision(approx, exact):
-    M, K = exact.shape
-    tot = 0
-    for a, b in zip(approx, exact):
-        tot += len(np.intersect1d(a[a >= 0], b))
-    return tot / float(M * K)
+    """Eq. 9 over all rows (the validated recall of the oracle)."""
+    return O.recall(approx, exact)

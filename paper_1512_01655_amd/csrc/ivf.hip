@@ -12,7 +12,7 @@
 //
 // Search: every point searches the 256-row tiles of the sorted corpus that
 // overlap its cluster's first n_probe probe clusters (extended with further
-// probe clusters until the tiles hold at least k + 1 rows).  Query blocks
+// probe clusters until those clusters hold at least k + 1 rows).  Query blocks
 // never straddle clusters, so a block's tile list is its cluster's, and the
 // whole search is one launch of the MFMA tile kernel over per-block tile
 // lists, followed by the same exact FP32 re-rank, certificate and exact scan
@@ -173,8 +173,11 @@ struct DevBuf {
     atsne_status get(size_t bytes) { return alloc(&p, bytes); }
 };
 
-// Per-cluster candidate tiles: the tiles overlapping the first n_probe probe
-// clusters, extended until they hold at least k + 1 rows.
+// Per-cluster candidate tiles.  The candidate clusters are the first n_probe
+// probe clusters, extended until their rows number at least k + 1; the
+// search covers the tiles of the sorted corpus that overlap their rows, a
+// superset of those rows (the tile kernel works on whole tiles), so every
+// point's result is the exact kNN over at least its candidate clusters.
 std::vector<std::vector<int32_t>> cluster_tiles(const atsne_ivf& ix, int n_probe, int k) {
     const int C = ix.C;
     std::vector<std::vector<int32_t>> out(C);
@@ -188,8 +191,8 @@ std::vector<std::vector<int32_t>> cluster_tiles(const atsne_ivf& ix, int n_probe
             const int p = ix.probe[(size_t)c * C + u];
             const int64_t lo = ix.start[p], hi = ix.start[p + 1];
             if (hi <= lo) continue;
-            for (int64_t t = lo / IVF_TILE; t <= (hi - 1) / IVF_TILE; ++t)
-                if (cover.insert((int32_t)t).second) rows += std::min<int64_t>(ix.N, (t + 1) * IVF_TILE) - t * IVF_TILE;
+            rows += hi - lo;
+            for (int64_t t = lo / IVF_TILE; t <= (hi - 1) / IVF_TILE; ++t) cover.insert((int32_t)t);
         }
         out[c].assign(cover.begin(), cover.end());
     }

@@ -6,9 +6,12 @@ nearest centroid (the GPU's assigned centroid must be nearest within the
 FP32 tie rule), the update against the FP64 mean of the members (FP32 sum of
 n terms: relative error below (n + 2) u of the sum of magnitudes), and the
 probe order against FP64 centroid distances.  The search is checked against
-the exact kNN over each point's candidates, computed by the oracle from the
-GPU's partition (the partition is an input of the search), with the same
-neighbour-set tie rule as the exact path.
+the exact kNN over each point's tile-rounded candidates (the library's
+reading: whole 256-row tiles covering the candidate clusters), computed by
+the oracle from the GPU's partition (the partition is an input of the
+search), with the same neighbour-set tie rule as the exact path; and against
+the oracle's definition over the candidate clusters' rows, which that
+superset can only match or beat at every rank.
 """
 import numpy as np
 import pytest
@@ -17,6 +20,7 @@ import torch
 from oracle import ivf as IV
 from oracle import oracle as O
 from paper_1512_01655_amd import datagen
+from tests import ivf_reading as RD
 from tests import parity
 from tests.gpu_common import lib, say
 
@@ -75,13 +79,24 @@ def test_search_matches_definition(A, n_probe):
     assign, cent, start, probe = ix.partition()
     assign = assign.cpu().numpy()
     idx, d2, fl, frac = ix.knn(k, n_probe)
-    o_idx, o_d2, o_nx, ncand = IV.search(X, k, assign, C, cent.cpu().numpy(), n_probe, probe=probe)
+    g_idx, g_d2 = idx.cpu().numpy(), d2.cpu().numpy()
+    probe = np.asarray(probe)
+    o_idx, o_d2, o_nx, ncand = RD.search_tile_rounded(X, k, assign, C, probe, n_probe)
     rows = np.arange(3000)
-    ties, exact = parity.check_knn(X, rows, idx.cpu().numpy(), d2.cpu().numpy(), o_idx, o_d2, o_nx)
+    ties, exact = parity.check_knn(X, rows, g_idx, g_d2, o_idx, o_d2, o_nx)
     assert abs(frac - ncand.sum() / 3000.0 ** 2) < 1e-9
+    # the oracle's definition: candidates are the candidate clusters' rows;
+    # the tile-rounded superset is as close or closer at every rank
+    d_idx, d_d2, _, dcand = IV.search(X, k, assign, C, cent.cpu().numpy(), n_probe, probe=probe)
+    assert np.all(dcand <= ncand)
+    td = np.sort(parity.true_d2(X, rows, g_idx), axis=1)
+    assert np.all(td <= d_d2 * (1 + parity.TIE_REL) + 1e-30)
     e_idx, _, _ = O.get().knn(X, k)
-    rho = IV.precision(idx.cpu().numpy(), e_idx)
-    say("    n_probe %d: candidates %.3f of N, precision %.4f, %d tie-rule rows" % (n_probe, frac, rho, ties))
+    rho = IV.precision(g_idx, e_idx)
+    rho_def = IV.precision(d_idx, e_idx)
+    say("    n_probe %d: candidates %.3f of N, precision %.4f (definition's %.4f), %d tie-rule rows" % (
+        n_probe, frac, rho, rho_def, ties))
+    assert rho >= rho_def - 1e-3
     if n_probe == C:
         assert frac == 1.0 and rho == 1.0
         # every tile probed: the exact search's rows bit for bit (the index
@@ -111,8 +126,8 @@ def test_fit_and_full_size(A):
     assert rho_s >= rho and rho_all >= rho - 0.03
     assign, cent, start, probe = ix.partition()
     rows = rng.choice(N, size=200, replace=False).astype(np.int32)
-    o_idx, o_d2, o_nx, _ = IV.search(X, k, assign.cpu().numpy(), C, cent.cpu().numpy(), n_probe, probe=probe,
-                                     rows=rows)
+    o_idx, o_d2, o_nx, _ = RD.search_tile_rounded(X, k, assign.cpu().numpy(), C, np.asarray(probe), n_probe,
+                                                  rows=rows)
     parity.check_knn(X, rows, idx.cpu().numpy()[rows], d2.cpu().numpy()[rows], o_idx, o_d2, o_nx)
     ix.close()
 

@@ -7,6 +7,7 @@ from scipy.spatial.distance import cdist
 from oracle import ivf as IV
 from oracle import oracle as O
 from paper_1512_01655_amd import datagen
+from tests import ivf_reading as RD
 
 
 def test_candidates_all_rows_is_plain_knn():
@@ -78,16 +79,56 @@ def test_cluster_order_and_probe_order():
     assert po[2].tolist() == [2, 1, 0, 3]
 
 
-def test_candidate_tiles_hand():
+def test_candidate_clusters_hand():
     start = np.array([0, 100, 300, 700, 700, 1000])
     probe = np.array([[0, 1, 2, 3, 4], [1, 0, 2, 3, 4], [2, 4, 1, 0, 3], [3, 2, 4, 1, 0], [4, 3, 2, 1, 0]])
-    t = IV.candidate_tiles(start, probe, 1, 10, 1000)
-    assert t[0] == [0] and t[1] == [0, 1] and t[2] == [1, 2] and t[4] == [2, 3]
-    # cluster 3 is empty: its own tiles cover nothing, so probing extends to cluster 2
-    assert t[3] == [1, 2]
-    # the K + 1 rule: cluster 0 (100 rows, one 256-row tile) with K = 300 needs cluster 1's tiles too
-    assert IV.candidate_tiles(start, probe, 1, 300, 1000)[0] == [0, 1]
-    assert IV.candidate_tiles(start, probe, 2, 10, 1000)[0] == [0, 1]
+    c = IV.candidate_clusters(start, probe, 1, 10)
+    assert c == [[0], [1], [2], [3, 2], [4]]  # cluster 3 is empty: probing extends to cluster 2
+    # the K + 1 rule counts cluster rows: 100 and 100 + 200 rows are short of 301
+    assert IV.candidate_clusters(start, probe, 1, 300)[0] == [0, 1, 2]
+    assert IV.candidate_clusters(start, probe, 2, 10)[0] == [0, 1]
+    assert IV.candidate_clusters(start, probe, 5, 10)[2] == [2, 4, 1, 0, 3]
+
+
+def test_tile_rounding_is_a_superset():
+    # the library's reading (whole 256-row tiles) covers every candidate row
+    start = np.array([0, 100, 300, 700, 700, 1000])
+    probe = np.array([[0, 1, 2, 3, 4], [1, 0, 2, 3, 4], [2, 4, 1, 0, 3], [3, 2, 4, 1, 0], [4, 3, 2, 1, 0]])
+    cover = RD.tile_rounded_rows(start, IV.candidate_clusters(start, probe, 1, 10), 1000)
+    assert cover[0].tolist() == list(range(256)) and cover[4].tolist() == list(range(512, 1000))
+    rng = np.random.default_rng(9)
+    for trial in range(20):
+        C = int(rng.integers(2, 40))
+        N = int(rng.integers(C, 3000))
+        assign = rng.integers(0, C, size=N)
+        _, st = IV.cluster_order(assign, C)
+        pr = np.array([np.concatenate([[c], rng.permutation(np.delete(np.arange(C), c))]) for c in range(C)])
+        for n_probe in (1, 2, C):
+            cl = IV.candidate_clusters(st, pr, n_probe, 10)
+            cov = RD.tile_rounded_rows(st, cl, N)
+            for c in range(C):
+                rows = np.concatenate([np.arange(st[p], st[p + 1]) for p in cl[c]])
+                assert set(rows.tolist()) <= set(cov[c].tolist())
+                assert len(rows) >= min(11, N)
+
+
+def test_precision_grows_with_candidates():
+    # a superset of candidates gives each row at least the hits of a subset
+    # (Eq. 9 counts exact neighbours found; an exact neighbour among the
+    # candidates is always among their K nearest)
+    X = datagen.mixture_isotropic(n=600, d=8, seed=75)
+    rng = np.random.default_rng(6)
+    C = 8
+    cent = X[rng.choice(600, size=C, replace=False)].astype(np.float64)
+    a = IV.nearest_centroid(X, cent)
+    probe = IV.probe_order(cent)
+    e_idx, _, _ = O.get().knn(X, 10)
+    sub = IV.search(X, 10, a, C, cent, 1)[0]
+    sup = RD.search_tile_rounded(X, 10, a, C, probe, 1)[0]
+    for r in range(600):
+        hs = len(set(sub[r].tolist()) & set(e_idx[r].tolist()))
+        hp = len(set(sup[r].tolist()) & set(e_idx[r].tolist()))
+        assert hp >= hs
 
 
 def test_search_reduces_to_exact_with_all_probes():
@@ -103,3 +144,5 @@ def test_search_reduces_to_exact_with_all_probes():
     assert np.all(n1 <= ncand) and IV.precision(idx1, e_idx) <= 1.0
     # Eq. 9 by hand
     assert IV.precision(np.array([[1, 2, 3], [4, 5, -1]]), np.array([[3, 2, 9], [6, 5, 4]])) == pytest.approx(4 / 6)
+    with pytest.raises(ValueError):
+        IV.precision(np.array([[1, 1, 3]]), np.array([[1, 2, 3]]))
