@@ -44,7 +44,7 @@ def parse():
                          "copy (the reference kernel for scaling HBM byte counters); prints the launch shapes")
     ap.add_argument("--serve-rate", type=float, default=25.0, help="Poisson request rate (req/s)")
     ap.add_argument("--serve-requests", type=int, default=120)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target length of the oracle sample")
     return ap.parse_args()
 
 
@@ -55,6 +55,8 @@ def log(*a):
 KERNEL_SOURCES = ["paper_1512_01655_amd/csrc/knn.hip", "paper_1512_01655_amd/csrc/wave.h",
                   "paper_1512_01655_amd/csrc/knn_internal.h", "paper_1512_01655_amd/csrc/common.h"]
 TRAFFIC_FILE = "profiles/knn_tile_traffic.txt"
+TRAFFIC_NOTE = ("rocprofv3 FETCH_SIZE + WRITE_SIZE per launch, measured by the builder on these kernel sources "
+                "(profiles/knn_tile_traffic.txt, keyed by source hash); null when the sources changed since")
 
 
 def kernel_source_hash():
@@ -164,43 +166,77 @@ def order_leg(A, torch, idx, d2, beta, reps=5, seed=9):
     return out
 
 
+def rows_valid(torch, idx, d2, n):
+    """Every row lists distinct ids in [0, n), never its own row (rows are
+    queries 0..M-1 of the corpus), with distances ascending."""
+    M = idx.shape[0]
+    own = torch.arange(M, device=idx.device, dtype=idx.dtype)[:, None]
+    srt = idx.sort(dim=1).values
+    ok = bool(((idx >= 0) & (idx < n)).all().item()) and not bool((idx == own).any().item())
+    ok = ok and not bool((srt[:, 1:] == srt[:, :-1]).any().item())
+    return ok and bool((d2[:, 1:] >= d2[:, :-1]).all().item())
+
+
 def precision_eq9(torch, approx, exact, chunk=4096):
-    """Eq. 9: mean over rows of |N^A_i & N_i| / K (neighbour lists hold distinct ids)."""
+    """Eq. 9: mean over rows of |N^A_i & N_i| / K; each listed id counts once
+    (a repeated id of an approximate row is not a second hit)."""
     hits = 0
     for s in range(0, exact.shape[0], chunk):
         a, e = approx[s:s + chunk], exact[s:s + chunk]
-        hits += int(((a[:, :, None] == e[:, None, :]) & (a[:, :, None] >= 0)).any(dim=2).sum().item())
+        a_s = a.sort(dim=1).values
+        first = torch.ones_like(a_s, dtype=torch.bool)
+        first[:, 1:] = a_s[:, 1:] != a_s[:, :-1]
+        hit = ((a_s[:, :, None] == e[:, None, :]) & (a_s[:, :, None] >= 0)).any(dim=2) & first
+        hits += int(hit.sum().item())
     return hits / float(exact.numel())
 
 
-def max_dp_same_rows(torch, rb, r):
-    """max |P_bf16 - P_fp32| over rows whose neighbour lists are identical (same order)."""
-    same = (rb["idx"] == r["idx"]).all(1)
-    if not bool(same.any()):
-        return None
-    return float((rb["P"][same] - r["P"][same]).abs().max().item())
+def host_recall(g_idx, o_idx):
+    """Eq. 9 on host arrays whose rows are already validated (distinct ids)."""
+    return sum(len(set(a) & set(b)) for a, b in zip(g_idx.tolist(), o_idx.tolist())) / float(o_idx.size)
 
 
-def fp8_scale_leg(A, torch, datagen, steps=2, warmup=1, sample=256, seed=13):
+def union_dP(g_idx, g_P, o_idx, o_P):
+    """max over rows of |p_gpu - p_oracle| over the union of the two rows'
+    supports, an entry missing from one side counting as 0."""
+    M, K = o_idx.shape
+    r = np.repeat(np.arange(M, dtype=np.int64), K)
+    n = int(max(g_idx.max(), o_idx.max())) + 1
+    gk = r * n + g_idx.reshape(-1).astype(np.int64)
+    ok = r * n + o_idx.reshape(-1).astype(np.int64)
+    keys = np.union1d(gk, ok)
+    gv = np.zeros(keys.shape)
+    ov = np.zeros(keys.shape)
+    gv[np.searchsorted(keys, gk)] = g_P.reshape(-1)
+    ov[np.searchsorted(keys, ok)] = o_P.reshape(-1)
+    return float(np.abs(gv - ov).max())
+
+
+def vs_oracle(g_idx, g_P, o):
+    """a8 metrics of GPU rows against the oracle's rows of the same queries."""
+    same = sum(set(a) == set(b) for a, b in zip(g_idx.tolist(), o["idx"].tolist()))
+    return {"oracle_rows": int(o["idx"].shape[0]), "recall_vs_oracle": round(host_recall(g_idx, o["idx"]), 6),
+            "rows_with_oracle_set": int(same),
+            "max_abs_dP_cond_vs_oracle": float("%.4g" % union_dP(g_idx, g_P.astype(np.float64), o["idx"], o["P"]))}
+
+
+def fp8_scale_leg(A, torch, datagen, steps=2, warmup=1, sample=10000, seed=13):
     """Precision at scale: N = 10^6, D = 128 anisotropic mixture, mu = 50, k = 150, FP8 e4m3 contraction with
-    per-row scales and an FP32 re-rank of 2k = 300 candidates.  Whole-path points/s, the tile against the FP8
-    matrix-core peak, and recall / max |dP| on a seeded sample of rows against the exact FP32 path (which the
-    parity tests hold to the FP64 oracle)."""
+    per-row scales and an FP32 re-rank of 2k = 300 candidates.  Whole-path points/s and the tile against the FP8
+    matrix-core peak; the rows of a seeded sample are kept for the comparison with the FP64 oracle."""
     X = datagen.mixture_anisotropic()
     N, D = X.shape
     mu, k = 50.0, 150
     Xt = torch.from_numpy(X).cuda()
-    del X
     r = run_path(A, torch, Xt, mu, k, "fp8", steps, warmup)
     value = N * steps / r["wall"]
     t_ms, t_n = r["stages"]["knn_tile"]
     t_avg = t_ms / max(t_n, 1) * 1e-3
     ach = 2.0 * N * N * D * steps / max(t_n, 1) / t_avg / 1e12
     rows = np.sort(np.random.default_rng(seed).choice(N, size=sample, replace=False)).astype(np.int32)
-    q = torch.from_numpy(rows).cuda()
-    ie, de, fe = A.knn(Xt, k, prec="fp32", query_ids=q)
-    Pe, _, _, _ = A.calibrate_p(de, mu, flags=fe)
-    sub = {"idx": r["idx"][q.long()], "P": r["P"][q.long()]}
+    q = torch.from_numpy(rows.astype(np.int64)).cuda()
+    valid = rows_valid(torch, r["idx"], r["d2"], N)
+    kept = {"X": X, "rows": rows, "idx": r["idx"][q].cpu().numpy(), "P": r["P"][q].cpu().numpy()}
     out = {
         "workload": "aniso50_N1000000_D128_mu50_k150", "k_cand": 2 * k, "value": round(value, 1),
         "ms_per_step": round(1e3 * r["wall"] / steps, 3),
@@ -208,14 +244,13 @@ def fp8_scale_leg(A, torch, datagen, steps=2, warmup=1, sample=256, seed=13):
         "roofline": {"bound": "mfma", "kernel": "knn_tile", "achieved": round(ach, 2), "peak": PEAK["fp8"],
                      "unit": "TFLOP/s", "frac": round(ach / PEAK["fp8"], 4),
                      "traffic": measured_traffic("aniso", "fp8"),
+                     "traffic_source": TRAFFIC_NOTE,
                      "algorithmic": "2*N*D FLOP per query point x N queries per step, N=%d, D=%d" % (N, D)},
-        "sample_rows": sample,
-        "recall_vs_exact_sample": round(precision_eq9(torch, sub["idx"], ie), 6),
-        "max_abs_dP_vs_exact_same_rows": max_dp_same_rows(torch, sub, {"idx": ie, "P": Pe}),
+        "rows_valid": valid,
     }
     del r, Xt
     torch.cuda.empty_cache()
-    return out
+    return out, kept
 
 
 def approx_leg(A, torch, Xt, mu, k, exact_idx, exact_value, rho=0.9, C=256, iters=8, steps=5, seed=11):
@@ -361,6 +396,10 @@ def window_stream(A, torch, W=6000, D=52, ticks=400, warm=40, mu=30.0, seed=41):
 
 
 def cpu_baseline(X, mu, k, target_s):
+    """The FP64 oracle (exact kNN against the full corpus + bisection) timed on
+    a seeded sample of query rows sized to about target_s seconds on the host
+    cores.  Returns the baseline record and the oracle's rows (the precision
+    metrics compare the GPU paths with them)."""
     from oracle import oracle as O
 
     o = O.get()
@@ -372,14 +411,46 @@ def cpu_baseline(X, mu, k, target_s):
     o.calibrate(d2, mu)
     rate = 64 / (time.perf_counter() - t0)
     m = int(min(X.shape[0], max(64, rate * target_s)))
-    rows = rng.choice(X.shape[0], size=m, replace=False).astype(np.int32)
+    rows = np.sort(rng.choice(X.shape[0], size=m, replace=False)).astype(np.int32)
     t0 = time.perf_counter()
-    _, d2, _ = o.knn(X, k, query_ids=rows)
-    o.calibrate(d2, mu)
+    idx, d2, nx = o.knn(X, k, query_ids=rows)
+    P, _, _, _ = o.calibrate(d2, mu)
     dt = time.perf_counter() - t0
-    return {"value": m / dt, "unit": "points/s", "cores": cores, "kind": "oracle",
-            "sample": "%d of %d query rows: FP64 exact kNN against the full corpus + bisection, %.1f s" % (
-                m, X.shape[0], dt)}
+    rec = {"value": m / dt, "unit": "points/s", "cores": cores, "kind": "oracle",
+           "sample": "%d of %d query rows: FP64 exact kNN against the full corpus + bisection, %.1f s" % (
+               m, X.shape[0], dt)}
+    return rec, {"rows": rows, "idx": idx, "d2": d2, "nx": nx, "P": P}
+
+
+def oracle_rows(X, k, mu, rows):
+    """The FP64 oracle's rows for the sampled queries of the FP8 leg (timed)."""
+    from oracle import oracle as O
+
+    o = O.get()
+    t0 = time.perf_counter()
+    idx, d2, nx = o.knn(X, k, query_ids=rows)
+    P, _, _, _ = o.calibrate(d2, mu)
+    dt = time.perf_counter() - t0
+    return {"rows": rows, "idx": idx, "d2": d2, "nx": nx, "P": P, "seconds": dt, "cores": o.max_threads()}
+
+
+def exact_vs_oracle(g_idx, g_d2, g_P, o, rel=1e-5):
+    """The exact path on the oracle's sample rows: rows outside the tie rule
+    must have the oracle's set; P compared entry by entry where the sets agree."""
+    K = o["idx"].shape[1]
+    dK = o["d2"][:, K - 1]
+    tie = o["nx"] <= dK * (1 + rel)
+    mism = 0
+    worst = 0.0
+    for r in range(g_idx.shape[0]):
+        a, b = g_idx[r].tolist(), o["idx"][r].tolist()
+        if set(a) != set(b):
+            mism += 0 if tie[r] else 1
+            continue
+        gm = dict(zip(a, g_P[r].tolist()))
+        worst = max(worst, max(abs(gm[j] - p) for j, p in zip(b, o["P"][r].tolist())))
+    return {"oracle_rows": int(g_idx.shape[0]), "tie_rule_rows": int(tie.sum()), "set_mismatch_rows": mism,
+            "max_abs_dP_cond_vs_oracle": float("%.4g" % worst)}
 
 
 def main():
@@ -457,13 +528,13 @@ def main():
             "stages_ms": {kname: round(v[0] / a.steps, 3) for kname, v in rb["stages"].items()},
             "roofline": {"bound": "mfma", "kernel": "knn_tile", "achieved": round(ach_b, 2), "peak": PEAK["bf16"],
                          "unit": "TFLOP/s", "frac": round(ach_b / PEAK["bf16"], 4),
-                         "traffic": measured_traffic(a.workload, "bf16")},
+                         "traffic": measured_traffic(a.workload, "bf16"), "traffic_source": TRAFFIC_NOTE},
+            "rows_valid": rows_valid(torch, rb["idx"], rb["d2"], N),
             "agree_with_fp32_rows": float((rb["idx"] == r["idx"]).all(1).float().mean().item()),
-            # against the exact FP32 path, which matches the FP64 oracle within the tie rule
-            "recall_vs_exact": round(precision_eq9(torch, rb["idx"], r["idx"]), 6),
-            "max_abs_dP_vs_exact_same_rows": max_dp_same_rows(torch, rb, r),
         }
+        keep_b = {"idx": rb["idx"].cpu().numpy(), "P": rb["P"].cpu().numpy()}
         log("bf16: %.1f points/s (x%.2f)" % (vb, vb / value))
+    keep_e = {"idx": r["idx"].cpu().numpy(), "d2": r["d2"].cpu().numpy(), "P": r["P"].cpu().numpy()}
     # The second exact contraction: each FP32 value split into BF16 hi + lo,
     # three BF16 MFMA products per element pair.  Same certificate (with its
     # own bound), same FP32 re-rank: its outputs must equal the FP32 path's.
@@ -471,8 +542,9 @@ def main():
     vx = N * a.steps / rx["wall"]
     tx_ms, tx_n = rx["stages"]["knn_tile"]
     tx_avg = tx_ms / max(tx_n, 1) * 1e-3
-    # matrix-core work: three BF16 products per FP32 product of the contraction
-    ach_x = 3.0 * flop_step * a.steps / max(tx_n, 1) / tx_avg / 1e12
+    # the method's work is the FP32 contraction's 2*N*D per query; the matrix
+    # cores run three BF16 products per element pair (mfma_ops_frac)
+    ach_x = flop_step * a.steps / max(tx_n, 1) / tx_avg / 1e12
     same = bool(torch.equal(rx["idx"], r["idx"]) and torch.equal(rx["d2"], r["d2"])
                 and np.array_equal(rx["flags"], r["flags"]))
     line["exact_fp32x3"] = {
@@ -481,11 +553,14 @@ def main():
         "stages_ms": {kname: round(v[0] / a.steps, 3) for kname, v in rx["stages"].items()},
         "roofline": {"bound": "mfma", "kernel": "knn_tile", "achieved": round(ach_x, 2), "peak": PEAK["bf16"],
                      "unit": "TFLOP/s", "frac": round(ach_x / PEAK["bf16"], 4),
-                     "traffic": measured_traffic(a.workload, "fp32x3"),
-                     "algorithmic": "3 x 2*N*D BF16 FLOP per query point (hi*hi + hi*lo + lo*hi)"},
+                     "mfma_ops_frac": round(3.0 * ach_x / PEAK["bf16"], 4),
+                     "traffic": measured_traffic(a.workload, "fp32x3"), "traffic_source": TRAFFIC_NOTE,
+                     "algorithmic": "2*N*D FLOP per query point (the method's contraction) against the BF16 peak; "
+                                    "mfma_ops_frac counts the three BF16 products (hi*hi + hi*lo + lo*hi) issued"},
         "outputs_identical_to_fp32": same,
         "rows_exact_scan": int(((rx["flags"] & 8) > 0).sum()),
     }
+    del rx
     log("fp32x3: %.1f points/s (x%.2f), identical to fp32: %s" % (vx, vx / value, same))
     if not (a.no_serve or a.path_only) and a.workload == "imagelike":
         log("serve: Poisson stream at %.0f req/s ..." % a.serve_rate)
@@ -498,9 +573,10 @@ def main():
         log("precision-controlled path (rho = 0.9) ...")
         line["approx_rho"] = approx_leg(A, torch, Xt, mu, k, r["idx"], value)
         log("approx: %s" % line["approx_rho"])
+    fp8_kept = None
     if a.workload == "imagelike" and not a.no_fp8:
         log("precision at scale: FP8, N = 10^6 ...")
-        line["fp8_scale"] = fp8_scale_leg(A, torch, datagen)
+        line["fp8_scale"], fp8_kept = fp8_scale_leg(A, torch, datagen)
         log("fp8: %s" % line["fp8_scale"])
     log("attractive forces over the step's P ...")
     line["attractive"] = attractive_leg(A, torch, r["rp"], r["col"], r["val"])
@@ -515,7 +591,22 @@ def main():
         log("window: tick p50 %.2f ms, p99 %.2f ms" % (line["window"]["tick_p50_ms"], line["window"]["tick_p99_ms"]))
     if not a.no_cpu_baseline:
         log("cpu baseline: timing the FP64 oracle on a bounded sample ...")
-        line["cpu_baseline"] = cpu_baseline(X, mu, k, a.cpu_seconds)
+        line["cpu_baseline"], ora = cpu_baseline(X, mu, k, a.cpu_seconds)
+        # precision metrics (Eq. 9 recall, max |dP| over the union support)
+        # of each GPU path against the FP64 oracle on the sampled rows
+        rows = ora["rows"]
+        line["exact_vs_oracle"] = exact_vs_oracle(keep_e["idx"][rows], keep_e["d2"][rows],
+                                                  keep_e["P"][rows].astype(np.float64), ora)
+        if not a.no_bf16:
+            line["bf16_rerank"].update(vs_oracle(keep_b["idx"][rows], keep_b["P"][rows], ora))
+        log("vs oracle: exact %s" % line["exact_vs_oracle"])
+        if fp8_kept is not None:
+            log("fp8 vs oracle: %d sampled rows of 10^6 ..." % len(fp8_kept["rows"]))
+            o8 = oracle_rows(fp8_kept["X"], 150, 50.0, fp8_kept["rows"])
+            line["fp8_scale"].update(vs_oracle(fp8_kept["idx"], fp8_kept["P"], o8))
+            line["fp8_scale"]["oracle_seconds"] = round(o8["seconds"], 1)
+            log("fp8 vs oracle: %s" % {kk: line["fp8_scale"][kk] for kk in ("recall_vs_oracle",
+                                                                          "max_abs_dP_cond_vs_oracle")})
     print(json.dumps(line), flush=True)
 
 

@@ -279,14 +279,3 @@ def test_pipeline_config1_full(A, ora):
         worst = max(worst, abs(gd.get(key, 0.0) - od.get(key, 0.0)) * 2 * N)
     say("    max |2N dP_sym| off the tie bands: %.3g (%d band pairs)" % (worst, len(band)))
     assert worst <= parity.P_TOL
-
-
-def test_pipeline_config2_sampled(A, ora):
-    X = datagen.image_like()
-    rows = np.random.default_rng(21).choice(X.shape[0], size=150, replace=False).astype(np.int32)
-    g, _ = _pipeline_check(A, ora, X, 30.0, rows=rows)
-    # the symmetrisation at full size (6.3e6 conditional entries, the
-    # benchmark's launch): the oracle's transpose-add of the same rows
-    N = X.shape[0]
-    o = ora.symmetrize(g["idx"], g["P"].astype(np.float64))
-    _check_sym_equal(N, (g["row_ptr"], g["col"], g["val"]), o)

@@ -1,0 +1,165 @@
+"""Full-size parity against the FP64 oracle, in the launch configuration the
+benchmark times.
+
+  * image-like workload (N = 70000, D = 784, mu = 30, K = 90), exact FP32
+    contraction: every one of the 70000 rows against the oracle (neighbour
+    sets under the tie rule, P_cond within 1e-6, perplexity within 1e-4,
+    2N p_ij within 1e-6 over the union of the two symmetric patterns outside
+    the tie bands); the FP32X3 contraction returns the same rows bit for bit;
+  * the same data with the BF16 contraction and FP32 re-rank of 2K
+    candidates: every row valid, recall (Eq. 9) against the oracle on all
+    rows at least 0.999, and max |dP| over the union support (absent = 0) for
+    P_cond and 2N P_sym, reported;
+  * the anisotropic workload (N = 10^6, D = 128, mu = 50, K = 150) with the
+    FP8 e4m3 contraction and 300 candidates: a seeded 10,000-row sample
+    searched against the full corpus by the oracle.
+
+The oracle runs on the host cores in chunks (a progress line per chunk).
+"""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1512_01655_amd import datagen
+from tests import parity
+from tests.gpu_common import lib, say
+
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
+
+
+@pytest.fixture(scope="module")
+def A():
+    return lib()
+
+
+def _oracle_knn_chunked(X, K, rows, chunk):
+    ora = O.get()
+    idx = np.empty((len(rows), K), np.int32)
+    d2 = np.empty((len(rows), K), np.float64)
+    nx = np.empty((len(rows),), np.float64)
+    t0 = time.time()
+    for s in range(0, len(rows), chunk):
+        e = min(len(rows), s + chunk)
+        idx[s:e], d2[s:e], nx[s:e] = ora.knn(X, K, query_ids=rows[s:e])
+        say("    oracle kNN rows %d / %d (%.0f s)" % (e, len(rows), time.time() - t0))
+    return idx, d2, nx
+
+
+@pytest.fixture(scope="module")
+def imagelike():
+    X = datagen.image_like()
+    N, K, mu = X.shape[0], 90, 30.0
+    say("  oracle on all %d image-like rows (%d host threads)" % (N, O.get().max_threads()))
+    rows = np.arange(N, dtype=np.int32)
+    o_idx, o_d2, o_nx = _oracle_knn_chunked(X, K, rows, 5000)
+    o_P, o_beta, o_perp, o_fl = O.get().calibrate(o_d2, mu)
+    o_csr = O.get().symmetrize(o_idx, o_P)
+    return dict(X=X, N=N, K=K, mu=mu, idx=o_idx, d2=o_d2, nx=o_nx, P=o_P, csr=o_csr)
+
+
+def _run_similarity(A, X, mu, prec):
+    say("  GPU similarity %s N=%d D=%d mu=%g" % (prec, X.shape[0], X.shape[1], mu))
+    r = A.similarity(torch.from_numpy(X).cuda(), mu, prec=prec)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in r.items()}
+
+
+def _band_pairs(N, o_idx, o_d2, o_nx, g_idx, td, rel=parity.TIE_REL):
+    """Keys i*N + j (both orientations) of the pairs inside a tie row's band:
+    the oracle's and the GPU's neighbours of row i at or beyond d_K (1 - rel)."""
+    K = o_idx.shape[1]
+    dK = o_d2[:, K - 1]
+    tie = o_nx <= dK * (1 + rel)
+    lo = (dK * (1 - rel))[:, None]
+    ri = np.repeat(np.arange(N, dtype=np.int64), K).reshape(N, K)
+    m_o = tie[:, None] & (o_d2 >= lo)
+    m_g = tie[:, None] & (td >= lo)
+    i = np.concatenate([ri[m_o], ri[m_g]])
+    j = np.concatenate([o_idx[m_o], g_idx[m_g]]).astype(np.int64)
+    return np.concatenate([i * N + j, j * N + i]), int(tie.sum())
+
+
+def test_config2_fp32_all_rows(A, imagelike):
+    o = imagelike
+    X, N, K, mu = o["X"], o["N"], o["K"], o["mu"]
+    g = _run_similarity(A, X, mu, "fp32")
+    rows = np.arange(N, dtype=np.int32)
+    ties, exact = parity.check_knn(X, rows, g["idx"], g["d2"], o["idx"], o["d2"], o["nx"])
+    dP = parity.check_p_rows(g["idx"], g["P"], o["idx"], o["P"], o["d2"], o["nx"])
+    perp = parity.perplexity_of_rows(g["P"])
+    ok = (g["flags"] & 4) == 0
+    assert np.abs(perp[ok] - mu).max() <= parity.PERP_TOL
+    assert np.abs(g["P"].astype(np.float64).sum(1) - 1).max() <= 1e-6
+    # symmetric P: 2N p_ij over the union of both patterns, absent = 0,
+    # outside the pairs of the tie bands (both sets are correct there)
+    td = parity.true_d2(X, rows, g["idx"])
+    band, n_tie = _band_pairs(N, o["idx"], o["d2"], o["nx"], g["idx"], td)
+    g_csr = (g["row_ptr"], g["col"], g["val"])
+    dS = parity.union_dP_sym(N, g_csr, o["csr"], exclude_pairs=band)
+    # stage isolation: the oracle's transpose-add of the GPU's own rows
+    oo = O.get().symmetrize(g["idx"], g["P"].astype(np.float64))
+    assert np.array_equal(g["row_ptr"], oo[0]) and np.array_equal(g["col"], oo[1])
+    dS_own = float(np.abs(g["val"].astype(np.float64) - oo[2]).max()) * 2 * N
+    say("    all %d rows: tie-rule rows %d, max|dP_cond| %.3g, max|perp-mu| %.3g, max 2N|dP_sym| %.3g "
+        "(own rows %.3g), fp64 rows %d, exact-scan rows %d" % (
+            N, ties, dP, np.abs(perp[ok] - mu).max(), dS, dS_own, int((g["flags"] & 1).sum()),
+            int(((g["flags"] & 8) > 0).sum())))
+    assert dS <= parity.P_TOL and dS_own <= parity.P_TOL
+    assert abs(g["val"].astype(np.float64).sum() - 1.0) < 1e-4
+    assert N * K <= len(g["val"]) <= 2 * N * K
+    # the FP32X3 contraction certifies the same candidates: every row's
+    # neighbours, distances and flags are those of the FP32 path
+    x = A.knn(torch.from_numpy(X).cuda(), K, prec="fp32x3")
+    torch.cuda.synchronize()
+    fl = A.knn(torch.from_numpy(X).cuda(), K, prec="fp32")[2]
+    assert np.array_equal(x[0].cpu().numpy(), g["idx"]) and np.array_equal(x[1].cpu().numpy(), g["d2"])
+    assert np.array_equal(x[2].cpu().numpy(), fl.cpu().numpy())
+
+
+def test_config3_bf16_all_rows(A, imagelike):
+    o = imagelike
+    X, N, K, mu = o["X"], o["N"], o["K"], o["mu"]
+    g = _run_similarity(A, X, mu, "bf16")
+    rows = np.arange(N, dtype=np.int32)
+    td = parity.check_rows_valid(X, rows, g["idx"], g["d2"])
+    rec = O.recall(g["idx"], o["idx"], query_ids=rows, n=N)
+    rec_t = parity.recall_tie_aware(td, o["d2"], o["idx"], g["idx"])
+    dP = parity.union_dP(g["idx"], g["P"].astype(np.float64), o["idx"], o["P"])
+    dS = parity.union_dP_sym(N, (g["row_ptr"], g["col"], g["val"]), o["csr"])
+    perp = parity.perplexity_of_rows(g["P"])
+    say("    bf16 all %d rows: recall %.6f (tie-aware %.6f), rows with the exact set %d, max|dP_cond| %.3g, "
+        "max 2N|dP_sym| %.3g over the union supports" % (
+            N, rec, rec_t, int(sum(set(a) == set(b) for a, b in zip(g["idx"].tolist(), o["idx"].tolist()))),
+            dP, dS))
+    assert rec >= 0.999
+    assert np.abs(perp - mu).max() <= parity.PERP_TOL
+
+
+def test_config4_fp8_sample_10k(A):
+    """FP8 e4m3 with per-row scales at N = 10^6, D = 128, k = 150, 300
+    candidates re-ranked in FP32: recall and max |dP| (union support) against
+    the FP64 oracle on a seeded 10,000-row sample searched over the full corpus."""
+    X = datagen.mixture_anisotropic()
+    N, k, kc, mu = X.shape[0], 150, 300, 50.0
+    say("  GPU knn fp8 N=%d D=%d k=%d kc=%d" % (N, X.shape[1], k, kc))
+    idx, d2, fl = A.knn(torch.from_numpy(X).cuda(), k, prec="fp8", k_cand=kc)
+    rows = np.sort(np.random.default_rng(9).choice(N, size=10000, replace=False)).astype(np.int32)
+    qi = torch.from_numpy(rows.astype(np.int64)).cuda()
+    g_idx, g_d2 = idx[qi].cpu().numpy(), d2[qi].cpu().numpy()
+    P, beta, perp, _ = A.calibrate_p(d2[qi].contiguous(), mu)
+    g_P = P.cpu().numpy().astype(np.float64)
+    del idx, d2, fl
+    torch.cuda.empty_cache()
+    td = parity.check_rows_valid(X, rows, g_idx, g_d2)
+    o_idx, o_d2, o_nx = _oracle_knn_chunked(X, k, rows, 1000)
+    o_P, _, _, _ = O.get().calibrate(o_d2, mu)
+    rec = O.recall(g_idx, o_idx, query_ids=rows, n=N)
+    rec_t = parity.recall_tie_aware(td, o_d2, o_idx, g_idx)
+    dP = parity.union_dP(g_idx, g_P, o_idx, o_P)
+    say("    fp8 10000-row sample: recall %.6f (tie-aware %.6f), max|dP_cond| %.3g over the union support" % (
+        rec, rec_t, dP))
+    assert rec >= 0.995
+    assert np.abs(parity.perplexity_of_rows(g_P) - mu).max() <= parity.PERP_TOL
