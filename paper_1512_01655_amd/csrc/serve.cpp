@@ -27,6 +27,7 @@
 #include <algorithm>
 #include <atomic>
 #include <climits>
+#include <cstdlib>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -200,6 +201,9 @@ struct atsne_server {
     std::thread worker;
     atsne_serve_stats stats{};
     atsne_status fatal = ATSNE_OK;
+    // test hook: the n-th batch launch fails with E_NOMEM before touching the
+    // device (ATSNE_SERVE_FAIL_LAUNCH=n at creation; 0 = never)
+    int64_t fail_launch_at = 0, launch_attempts = 0;
 };
 
 namespace atsne {
@@ -243,8 +247,14 @@ void carve_request(Request& r) {
     }
 }
 
-// Launch one batch of row segments on a free batch slot.
-atsne_status launch_batch(atsne_server* s, BatchSlot& b, std::vector<Seg>& segs, int64_t rows) {
+// Launch one batch of row segments on a batch slot the worker has reserved
+// (called without the server lock: it reads only fields fixed at submission
+// and the slot's own buffers).
+atsne_status launch_batch(atsne_server* s, BatchSlot& b, const std::vector<Seg>& segs, int64_t rows) {
+    if (s->fail_launch_at > 0 && ++s->launch_attempts == s->fail_launch_at) {
+        set_error("injected failure of batch launch %lld (ATSNE_SERVE_FAIL_LAUNCH)", (long long)s->fail_launch_at);
+        return ATSNE_E_NOMEM;
+    }
     const int64_t R = s->max_batch_rows;
     int32_t* hq = b.h_desc;
     int32_t* hn = hq + R;
@@ -293,18 +303,6 @@ atsne_status launch_batch(atsne_server* s, BatchSlot& b, std::vector<Seg>& segs,
         ATSNE_HIP(hipMemcpyAsync(g.r->flags + g.r0, b.b_flags + g.b0, g.n, hipMemcpyDeviceToDevice, b.st));
     }
     ATSNE_HIP(hipEventRecord(b.ev, b.st));
-    b.segs = segs;
-    b.busy = true;
-    s->stats.launches++;
-    s->stats.rows_processed += rows;
-    int distinct = 0;
-    const Request* last = nullptr;
-    for (const Seg& g : segs)
-        if (g.r != last) {
-            ++distinct;
-            last = g.r;
-        }
-    s->stats.max_requests_per_launch = std::max<int32_t>(s->stats.max_requests_per_launch, distinct);
     return ATSNE_OK;
 }
 
@@ -383,52 +381,129 @@ void fail_request(atsne_server* s, Request& r, atsne_status st) {
     s->stats.completed++;
 }
 
+// A launch or commit failed: the server stops serving.  Every stream is
+// drained first (without the lock), so no copy or kernel still writes into a
+// request's result memory when that request is failed and may be released;
+// then every admitted and queued request fails with `st`, and later
+// submissions are refused.
+void fail_server(atsne_server* s, std::unique_lock<std::mutex>& lk, atsne_status st) {
+    s->fatal = st;
+    lk.unlock();
+    for (auto& b : s->slot)
+        if (b.st) (void)hipStreamSynchronize(b.st);
+    for (hipStream_t q : {s->s_copy, s->s_commit, s->s_finish})
+        if (q) (void)hipStreamSynchronize(q);
+    lk.lock();
+    for (auto& b : s->slot) {
+        b.segs.clear();
+        b.busy = false;
+    }
+    for (Request* r : s->active)
+        if (r->state != DONE) fail_request(s, *r, st);
+    for (Request* r : s->pending) fail_request(s, *r, st);
+    s->active.clear();
+    s->pending.clear();
+    s->cv_done.notify_all();
+}
+
+// The worker: admission, batch formation and commit ordering under the server
+// lock; every GPU call (copies, launches, commits) with the lock released, so
+// submitters and waiters never queue behind device work.  Only the worker
+// changes a request's progress fields, so they need no lock while it runs.
 void worker_loop(atsne_server* s) {
     (void)hipSetDevice(s->device);
     std::unique_lock<std::mutex> lk(s->mu);
+    struct Job {
+        BatchSlot* b;
+        std::vector<Seg> segs;
+        int64_t rows;
+    };
     for (;;) {
-        bool progress = false, copied = false;
-        // 1. admission: request slots and the result arena (HBM budget)
-        while (!s->pending.empty() && (int)s->active.size() < s->max_slots) {
-            Request* r = s->pending.front();
-            r->mem = s->arena.alloc(r->bytes);
-            if (!r->mem) break;  // wait for releases
-            s->pending.pop_front();
-            carve_request(*r);
-            r->state = r->kind == 2 ? FORWARD_DONE : ADMITTED;  // a delete searches nothing
-            r->t_admit = now_ms(s->t0);
-            (void)hipMemcpyAsync(r->row_ids, r->ids_host.data(), sizeof(int32_t) * r->n, hipMemcpyHostToDevice,
-                                 s->s_copy);
-            copied = true;
-            s->active.push_back(r);
-            s->stats.bytes_in_flight = s->arena.used();
-            s->stats.peak_bytes_in_flight = std::max(s->stats.peak_bytes_in_flight, s->arena.used());
-            s->stats.max_concurrent = std::max<int32_t>(s->stats.max_concurrent, (int32_t)s->active.size());
-            progress = true;
-        }
-        if (copied) (void)hipStreamSynchronize(s->s_copy);
-        // 2. batch formation on free slots: row segments from every admitted request
-        for (auto& b : s->slot) {
-            if (b.busy) continue;
-            std::vector<Seg> segs;
-            int64_t rows = 0;
+        bool progress = false;
+        std::vector<Request*> admitted, finishing;
+        std::vector<Job> jobs;
+        if (s->fatal == ATSNE_OK) {
+            // 1. admission: request slots and the result arena (HBM budget)
+            while (!s->pending.empty() && (int)s->active.size() < s->max_slots) {
+                Request* r = s->pending.front();
+                r->mem = s->arena.alloc(r->bytes);
+                if (!r->mem) break;  // wait for releases
+                s->pending.pop_front();
+                carve_request(*r);
+                r->state = r->kind == 2 ? FORWARD_DONE : ADMITTED;  // a delete searches nothing
+                r->t_admit = now_ms(s->t0);
+                admitted.push_back(r);
+                s->active.push_back(r);
+                s->stats.bytes_in_flight = s->arena.used();
+                s->stats.peak_bytes_in_flight = std::max(s->stats.peak_bytes_in_flight, s->arena.used());
+                s->stats.max_concurrent = std::max<int32_t>(s->stats.max_concurrent, (int32_t)s->active.size());
+            }
+            // 2. batch formation on free slots: row segments from every admitted request
+            for (auto& b : s->slot) {
+                if (b.busy) continue;
+                Job j{&b, {}, 0};
+                for (Request* r : s->active) {
+                    if (r->state != ADMITTED || r->next_row >= r->n) continue;
+                    const int64_t take = std::min<int64_t>(r->n - r->next_row, s->max_batch_rows - j.rows);
+                    if (take <= 0) break;
+                    j.segs.push_back(Seg{r, r->next_row, take, j.rows});
+                    r->next_row += take;
+                    j.rows += take;
+                }
+                if (j.rows == 0) break;
+                b.busy = true;
+                b.segs = j.segs;
+                jobs.push_back(std::move(j));
+            }
+            // 3. finishing: refines calibrate; inserts and deletes commit in order
             for (Request* r : s->active) {
-                if (r->state != ADMITTED || r->next_row >= r->n) continue;
-                const int64_t take = std::min<int64_t>(r->n - r->next_row, s->max_batch_rows - rows);
-                if (take <= 0) break;
-                segs.push_back(Seg{r, r->next_row, take, rows});
-                r->next_row += take;
-                rows += take;
+                if (r->state != FORWARD_DONE) continue;
+                if (r->kind != 1) {
+                    if (r->epoch != s->next_commit) continue;
+                    s->next_commit++;
+                }
+                r->state = FINISHING;
+                finishing.push_back(r);
             }
-            if (rows == 0) break;
-            atsne_status st = launch_batch(s, b, segs, rows);
-            if (st != ATSNE_OK) {
-                s->fatal = st;
-                for (const Seg& g : segs) fail_request(s, *g.r, st);
-            }
-            progress = true;
         }
-        // 3. batch completions
+        progress = !admitted.empty() || !jobs.empty() || !finishing.empty();
+        if (progress) {
+            lk.unlock();
+            atsne_status err = ATSNE_OK;
+            for (Request* r : admitted)
+                if (err == ATSNE_OK && hipMemcpyAsync(r->row_ids, r->ids_host.data(), sizeof(int32_t) * r->n,
+                                                      hipMemcpyHostToDevice, s->s_copy) != hipSuccess) {
+                    set_error("row id copy failed");
+                    err = ATSNE_E_HIP;
+                }
+            if (!admitted.empty() && err == ATSNE_OK && hipStreamSynchronize(s->s_copy) != hipSuccess) {
+                set_error("row id copy failed");
+                err = ATSNE_E_HIP;
+            }
+            for (Job& j : jobs)
+                if (err == ATSNE_OK) err = launch_batch(s, *j.b, j.segs, j.rows);
+            for (Request* r : finishing)
+                if (err == ATSNE_OK)
+                    err = r->kind == 1 ? finish_refine(s, *r) : (r->kind == 0 ? commit_insert(s, *r) : commit_delete(s, *r));
+            lk.lock();
+            for (const Job& j : jobs) {
+                s->stats.launches++;
+                s->stats.rows_processed += j.rows;
+                int distinct = 0;
+                const Request* last = nullptr;
+                for (const Seg& g : j.segs)
+                    if (g.r != last) {
+                        ++distinct;
+                        last = g.r;
+                    }
+                s->stats.max_requests_per_launch = std::max<int32_t>(s->stats.max_requests_per_launch, distinct);
+            }
+            if (err != ATSNE_OK) {
+                fail_server(s, lk, err);
+                continue;
+            }
+        }
+        // 4. batch completions
         for (auto& b : s->slot) {
             if (!b.busy || hipEventQuery(b.ev) != hipSuccess) continue;
             for (const Seg& g : b.segs) {
@@ -439,25 +514,7 @@ void worker_loop(atsne_server* s) {
             b.busy = false;
             progress = true;
         }
-        // 4. finishing: refines calibrate; inserts commit in epoch order
-        for (Request* r : s->active) {
-            if (r->state != FORWARD_DONE) continue;
-            atsne_status st = ATSNE_OK;
-            if (r->kind == 1) {
-                st = finish_refine(s, *r);
-            } else {
-                if (r->epoch != s->next_commit) continue;
-                st = r->kind == 0 ? commit_insert(s, *r) : commit_delete(s, *r);
-                s->next_commit++;
-            }
-            if (st != ATSNE_OK) {
-                s->fatal = st;
-                fail_request(s, *r, st);
-            } else {
-                r->state = FINISHING;
-            }
-            progress = true;
-        }
+        // 5. finished requests
         for (size_t i = 0; i < s->active.size();) {
             Request* r = s->active[i];
             if (r->state == FINISHING && hipEventQuery(r->fin) == hipSuccess) {
@@ -549,6 +606,7 @@ extern "C" atsne_status atsne_serve_create(const atsne_serve_config* cfg, const 
     s->cap_rows = c.capacity_rows > 0 ? std::max<int64_t>(c.capacity_rows, N) : 2 * N;
     s->max_batch_rows = c.max_batch_rows > 0 ? c.max_batch_rows : 8192;
     s->max_slots = c.max_slots > 0 ? c.max_slots : 8;
+    if (const char* f = std::getenv("ATSNE_SERVE_FAIL_LAUNCH")) s->fail_launch_at = std::atoll(f);
     const size_t budget = c.hbm_budget_bytes > 0 ? c.hbm_budget_bytes : ((size_t)4 << 30);
     auto fail = [&](atsne_status st) {
         destroy_impl(s);
@@ -660,11 +718,14 @@ extern "C" atsne_status atsne_serve_create(const atsne_serve_config* cfg, const 
 extern "C" atsne_status atsne_serve_submit_insert(atsne_server* s, const float* X_new, int32_t B, uint64_t* req_id) {
     clear_error();
     ATSNE_REQUIRE(s && X_new && req_id && B >= 1, ATSNE_E_INVALID_ARG, "bad arguments");
+    // latency is measured from the caller's call, staging included
+    const double t_call = now_ms(s->t0);
     std::lock_guard<std::mutex> sl(s->submit_mu);
     int64_t row0;
     {
         std::lock_guard<std::mutex> lk(s->mu);
         ATSNE_REQUIRE(!s->stop, ATSNE_E_INVALID_ARG, "server is shutting down");
+        ATSNE_REQUIRE(s->fatal == ATSNE_OK, s->fatal, "the server stopped after a failed launch or commit");
         ATSNE_REQUIRE(s->n_reserved + B <= s->cap_rows, ATSNE_E_NOMEM, "corpus capacity %lld rows exceeded",
                       (long long)s->cap_rows);
         row0 = s->n_reserved;
@@ -702,7 +763,7 @@ extern "C" atsne_status atsne_serve_submit_insert(atsne_server* s, const float* 
         std::lock_guard<std::mutex> lk(s->mu);
         r->id = s->next_id++;
         r->epoch = s->commits_submitted++;
-        r->t_submit = now_ms(s->t0);
+        r->t_submit = t_call;
         s->n_reserved += B;
         s->stats.corpus_rows = s->n_reserved;
         s->stats.submitted++;
@@ -721,6 +782,7 @@ extern "C" atsne_status atsne_serve_submit_refine(atsne_server* s, const int32_t
     ATSNE_REQUIRE(perplexity >= 1.f && perplexity <= SERVE_MAX_PERPLEXITY, ATSNE_E_K_RANGE,
                   "perplexity %g outside [1, %g]", (double)perplexity, (double)SERVE_MAX_PERPLEXITY);
     const int k = (int)std::floor(3.0 * perplexity);
+    const double t_call = now_ms(s->t0);
     std::lock_guard<std::mutex> sl(s->submit_mu);
     auto* r = new Request();
     r->kind = 1;
@@ -762,9 +824,14 @@ extern "C" atsne_status atsne_serve_submit_refine(atsne_server* s, const int32_t
     }
     {
         std::lock_guard<std::mutex> lk(s->mu);
-        ATSNE_REQUIRE(!s->stop, ATSNE_E_INVALID_ARG, "server is shutting down");
+        if (s->stop || s->fatal != ATSNE_OK) {
+            const atsne_status st = s->stop ? ATSNE_E_INVALID_ARG : s->fatal;
+            free_request(s, r);
+            set_error(s->stop ? "server is shutting down" : "the server stopped after a failed launch or commit");
+            return st;
+        }
         r->id = s->next_id++;
-        r->t_submit = now_ms(s->t0);
+        r->t_submit = t_call;
         s->stats.submitted++;
         s->all[r->id] = r;
         s->pending.push_back(r);
@@ -778,6 +845,7 @@ extern "C" atsne_status atsne_serve_submit_delete(atsne_server* s, const int32_t
                                                   uint64_t* req_id) {
     clear_error();
     ATSNE_REQUIRE(s && ids_host && req_id && M >= 1, ATSNE_E_INVALID_ARG, "bad arguments");
+    const double t_call = now_ms(s->t0);
     std::lock_guard<std::mutex> sl(s->submit_mu);
     auto* r = new Request();
     r->kind = 2;
@@ -787,10 +855,11 @@ extern "C" atsne_status atsne_serve_submit_delete(atsne_server* s, const int32_t
     int64_t n_alive;
     {
         std::lock_guard<std::mutex> lk(s->mu);
-        if (s->stop) {
+        if (s->stop || s->fatal != ATSNE_OK) {
+            const atsne_status st = s->stop ? ATSNE_E_INVALID_ARG : s->fatal;
             delete r;
-            set_error("server is shutting down");
-            return ATSNE_E_INVALID_ARG;
+            set_error(s->stop ? "server is shutting down" : "the server stopped after a failed launch or commit");
+            return st;
         }
         r->nlim = s->n_reserved;
         n_alive = s->n_reserved - s->n_deleted;
@@ -851,7 +920,7 @@ extern "C" atsne_status atsne_serve_submit_delete(atsne_server* s, const int32_t
         for (int32_t v : r->ids_host) s->h_death[v] = (int32_t)c;
         r->id = s->next_id++;
         r->epoch = s->commits_submitted++;
-        r->t_submit = now_ms(s->t0);
+        r->t_submit = t_call;
         s->n_deleted += M;
         s->stats.submitted++;
         s->all[r->id] = r;
@@ -917,6 +986,7 @@ extern "C" atsne_status atsne_serve_snapshot(atsne_server* s, int64_t cap_rows, 
     // wait for every submitted commit to be applied
     s->cv.notify_all();
     s->cv_done.wait(lk, [&] {
+        if (s->fatal != ATSNE_OK) return true;
         if (s->next_commit != s->commits_submitted) return false;
         for (Request* r : s->active)
             if (r->kind != 1) return false;
@@ -924,6 +994,7 @@ extern "C" atsne_status atsne_serve_snapshot(atsne_server* s, int64_t cap_rows, 
             if (r->kind != 1) return false;
         return true;
     });
+    ATSNE_REQUIRE(s->fatal == ATSNE_OK, s->fatal, "the server stopped after a failed launch or commit");
     const int64_t n = s->n_committed;
     *n_rows = n;
     *epoch = s->commits_submitted;

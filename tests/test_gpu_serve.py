@@ -332,3 +332,140 @@ def test_serve_delete_errors(A):
     assert r["status"] == 0 and not np.isin(r["idx"], [3, 7]).any()
     s.release(r["req_id"])
     s.close()
+
+
+# ---------------------------------------------------------------------------
+# Operating size: requests split across launches, refine rows against the
+# FP64 oracle, image-like corpus, failure of a batched launch
+# ---------------------------------------------------------------------------
+def _vs_oracle(X, r, ids, mu, sample=None, seed=0):
+    """Refine rows against the oracle's exact kNN and calibration at mu on the
+    request's corpus (all rows, or a seeded sample of them)."""
+    ids = np.asarray(ids, np.int32)
+    pos = np.arange(len(ids))
+    if sample is not None and sample < len(ids):
+        pos = np.sort(np.random.default_rng(seed).choice(len(ids), size=sample, replace=False))
+    k = int(math.floor(3 * mu))
+    o_idx, o_d2, o_nx = O.get().knn(X, k, query_ids=ids[pos])
+    o_P, _, _, _ = O.get().calibrate(o_d2, mu)
+    ties, _ = parity.check_knn(X, ids[pos], r["idx"][pos], r["d2"][pos], o_idx, o_d2, o_nx)
+    dP = parity.check_p_rows(r["idx"][pos], r["P"][pos], o_idx, o_P, o_d2, o_nx)
+    perp = parity.perplexity_of_rows(r["P"][pos])
+    assert np.abs(perp - mu).max() <= parity.PERP_TOL
+    return ties, dP
+
+
+def test_serve_split_launches_vs_oracle(A):
+    # 300-row launches: every request but the smallest spans several
+    # launches on both batch slots; each result equals the plain entry
+    # points bit for bit and the oracle within the parity rules
+    X = _corpus(n=3000, seed=37)
+    s = A.Server(torch.from_numpy(X).cuda(), 30.0, max_batch_rows=300)
+    rng = np.random.default_rng(4)
+    reqs = []
+    for n, mu in [(1000, 10.0), (2500, 50.0), (299, 30.0), (300, 30.0), (301, 10.0), (7, 50.0), (1777, 30.0)]:
+        ids = rng.choice(X.shape[0], size=n, replace=False).astype(np.int32)
+        reqs.append((s.refine(ids, mu), ids, mu))
+    for rid, ids, mu in reqs:
+        r = s.wait(rid)
+        assert r["status"] == 0 and np.array_equal(r["row_ids"], ids)
+        _same(r, _standalone(A, X, ids, mu))
+        ties, dP = _vs_oracle(X, r, ids, mu)
+        say("    refine %d rows mu %g: tie-rule rows %d, max|dP| %.2g" % (len(ids), mu, ties, dP))
+        s.release(rid)
+    st = s.stats()
+    say("    stats %s" % st)
+    assert st["launches"] >= sum(len(x[1]) for x in reqs) // 300 and st["max_requests_per_launch"] >= 2
+    s.close()
+
+
+def test_serve_imagelike_alone_vs_mix(A):
+    # an image-like corpus (D = 784) with refines larger than one launch
+    # (8192 rows by default): the same requests alone and in the mix give the
+    # same bits, and every refine matches the oracle on its corpus version
+    X0 = datagen.image_like(n=20000, noise_seed=91)
+    pts = datagen.image_like(n=2200, noise_seed=92)
+    rng = np.random.default_rng(5)
+    seq, n = [], X0.shape[0]
+    for B, (m, mu) in zip([1500, 700, 0], [(10000, 30.0), (9000, 10.0), (12000, 50.0)]):
+        seq.append(("r", rng.choice(n, size=m, replace=False).astype(np.int32), mu))
+        if B:
+            off = n - X0.shape[0]
+            seq.append(("i", pts[off:off + B]))
+            n += B
+    say("  serve image-like: %d requests, alone" % len(seq))
+    alone, snap_a, _ = _run_sequence_cap(A, X0, seq, 30.0, True, X0.shape[0] + 2300)
+    say("  serve image-like: same requests in the mix")
+    mix, snap_m, st = _run_sequence_cap(A, X0, seq, 30.0, False, X0.shape[0] + 2300)
+    say("    mix stats %s" % st)
+    assert st["max_concurrent"] >= 2 and st["launches"] >= 5
+    for a, b in zip(alone, mix):
+        assert a["status"] == 0 and b["status"] == 0 and a["epoch"] == b["epoch"]
+        _same(a, b, keys=("row_ids", "idx", "d2", "P", "beta", "flags"))
+    assert np.array_equal(snap_a[1], snap_m[1]) and np.array_equal(snap_a[3], snap_m[3])
+    Xfull = np.concatenate([X0, pts[:n - X0.shape[0]]])
+    n = X0.shape[0]
+    for i, (item, r) in enumerate(zip(seq, alone)):
+        if item[0] == "r":
+            ties, dP = _vs_oracle(Xfull[:n], r, item[1], item[2], sample=300, seed=i)
+            say("    refine %d rows mu %g vs oracle (300 sampled): tie-rule rows %d, max|dP| %.2g" % (
+                len(item[1]), item[2], ties, dP))
+        else:
+            n += item[1].shape[0]
+
+
+def _run_sequence_cap(A, X0, seq, mu0, wait_each, cap):
+    s = A.Server(torch.from_numpy(X0).cuda(), mu0, capacity_rows=cap)
+    rids, out = [], []
+    for item in seq:
+        rid = s.insert(torch.from_numpy(item[1]).cuda()) if item[0] == "i" else s.refine(item[1], item[2])
+        if wait_each:
+            out.append(s.wait(rid))
+            s.release(rid)
+        else:
+            rids.append(rid)
+    for rid in rids:
+        out.append(s.wait(rid))
+        s.release(rid)
+    snap = s.snapshot()
+    st = s.stats()
+    s.close()
+    return out, snap, st
+
+
+def test_serve_failed_launch_fails_every_request(A, monkeypatch):
+    # the second batched launch fails on the host before touching the device
+    # (a forced E_NOMEM): every request in flight or queued completes with
+    # that status once the streams have drained, later submissions and
+    # snapshots are refused, and the server still shuts down
+    import time
+
+    X = _corpus(n=3000, seed=38)
+    monkeypatch.setenv("ATSNE_SERVE_FAIL_LAUNCH", "2")
+    s = A.Server(torch.from_numpy(X).cuda(), 30.0, max_batch_rows=300, capacity_rows=4000)
+    monkeypatch.delenv("ATSNE_SERVE_FAIL_LAUNCH")
+    rng = np.random.default_rng(6)
+    rids = [s.refine(rng.choice(3000, size=1000, replace=False).astype(np.int32), 30.0) for _ in range(3)]
+    rids.append(s.insert(torch.from_numpy(_corpus(n=200, seed=39)).cuda()))
+    rids.append(s.refine(rng.choice(3000, size=50, replace=False).astype(np.int32), 10.0))
+    deadline = time.time() + 60
+    res = {}
+    while len(res) < len(rids) and time.time() < deadline:
+        for rid in rids:
+            if rid not in res:
+                r = s.poll(rid, fetch=False)
+                if r is not None:
+                    res[rid] = r
+        time.sleep(0.01)
+    assert len(res) == len(rids), "requests did not complete after a failed launch"
+    st = [res[r]["status"] for r in rids]
+    say("    statuses after the failed launch: %s" % st)
+    assert all(x == A.E_NOMEM for x in st)
+    with pytest.raises(A.AtsneError) as e:
+        s.refine(np.array([0, 1], np.int32), 10.0)
+    assert e.value.status == A.E_NOMEM
+    with pytest.raises(A.AtsneError):
+        s.snapshot()
+    for rid in rids:
+        s.release(rid)
+    s.close(force=False)
