@@ -105,14 +105,19 @@ atsne_status atsne_knn_workspace_size(int64_t N, int64_t M, int32_t D, atsne_pre
  *   k_cand   candidates re-ranked per row, k <= k_cand <= min(N-1, 1024);
  *            0 selects the default (FP32: k + max(32, k/2); BF16/FP8: 2k).
  *   nbr_idx  [N x k] int32 out: neighbour indices, ascending by (d, j).
- *   nbr_d2   [N x k] FP32 out: squared distances, FP32 direct difference of
- *            the FP32 rows (FP64 when ATSNE_FLAG_FP64_RERANKED).
+ *   nbr_d2   [N x k] FP32 out: squared distances of the FP32 rows, a
+ *            compensated FP32 direct difference rounded to FP32 (FP64 when
+ *            ATSNE_FLAG_FP64_RERANKED).
+ *   nbr_d2_lo [N x k] FP32 out (may be NULL): each distance's residual, so
+ *            that nbr_d2 + nbr_d2_lo is the distance to well below FP32
+ *            resolution; atsne_calibrate_p takes it to resolve distance
+ *            differences that FP32 rounding of nbr_d2 would blur.
  *   flags    [N] uint8 out (may be NULL): ATSNE_FLAG_FP64_RERANKED,
  *            ATSNE_FLAG_EXACT_SCAN.
  * Self is excluded by index; exact duplicates are neighbours at distance 0;
  * equal distances are ordered by the lower index.  Asynchronous. */
 atsne_status atsne_knn(const float* X, int64_t N, int32_t D, int64_t ld, atsne_precision prec, int32_t k,
-                       int32_t k_cand, int32_t* nbr_idx, float* nbr_d2, uint8_t* flags, void* ws,
+                       int32_t k_cand, int32_t* nbr_idx, float* nbr_d2, float* nbr_d2_lo, uint8_t* flags, void* ws,
                        size_t ws_bytes, void* stream);
 
 /* As atsne_knn for the M query rows query_ids[0..M) (device int32, each in
@@ -121,13 +126,21 @@ atsne_status atsne_knn(const float* X, int64_t N, int32_t D, int64_t ld, atsne_p
  * applied to a selection (Sec. 5.1). */
 atsne_status atsne_knn_subset(const float* X, int64_t N, int32_t D, int64_t ld, const int32_t* query_ids,
                               int64_t M, atsne_precision prec, int32_t k, int32_t k_cand, int32_t* nbr_idx,
-                              float* nbr_d2, uint8_t* flags, void* ws, size_t ws_bytes, void* stream);
+                              float* nbr_d2, float* nbr_d2_lo, uint8_t* flags, void* ws, size_t ws_bytes,
+                              void* stream);
 
 /* ----------------------------------------------------------- calibration -- */
 
 /* Perplexity calibration (Eq. 3, Eq. 4 restricted to the neighbour set of
  * Eq. 8), one wavefront per row, bisection on beta in FP32.
  *   nbr_d2     [N x k] FP32 squared neighbour distances (any order).
+ *   nbr_d2_lo  [N x k] FP32 residuals of nbr_d2 (as written by atsne_knn), or
+ *              NULL: the row's distances are then nbr_d2 + nbr_d2_lo.  With
+ *              them, p_{j|i} matches an FP64 calibration of the exact
+ *              distances to about 2e-7 on rows whose distances are close
+ *              together relative to their size (the image-like workload);
+ *              from FP32 distances alone the shift d_j - min d carries their
+ *              rounding (up to one ulp of d) into p.
  *   perplexity target mu, 1 <= mu < k.
  *   tol        stop when |e^H - mu| <= tol (<= 0: default 1e-5); bisection
  *              also stops when the bracket collapses to adjacent floats.
@@ -145,8 +158,8 @@ atsne_status atsne_knn_subset(const float* X, int64_t N, int32_t D, int64_t ld, 
  * An entry of +inf is absent (a removed neighbour, Sec. 5.3): it gets p = 0
  * and the row is calibrated over its present entries; a row with no more
  * than mu present entries is uniform over them and DEGENERATE. */
-atsne_status atsne_calibrate_p(const float* nbr_d2, int64_t N, int32_t k, float perplexity, float tol,
-                               int32_t max_iter, int32_t strict, float* P_cond, float* beta, float* perp,
+atsne_status atsne_calibrate_p(const float* nbr_d2, const float* nbr_d2_lo, int64_t N, int32_t k, float perplexity,
+                               float tol, int32_t max_iter, int32_t strict, float* P_cond, float* beta, float* perp,
                                uint8_t* flags, void* stream);
 
 /* -------------------------------------------------------- symmetrisation -- */

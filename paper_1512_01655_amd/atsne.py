@@ -85,9 +85,10 @@ def load(path: Path | None = None) -> ctypes.CDLL:
         "atsne_profile_enable": [_i32],
         "atsne_profile_read": [ctypes.c_char_p, _p, _p],
         "atsne_knn_workspace_size": [_i64, _i64, _i32, ctypes.c_int, _i32, _i32, _p],
-        "atsne_knn": [_p, _i64, _i32, _i64, ctypes.c_int, _i32, _i32, _p, _p, _p, _p, _sz, _p],
-        "atsne_knn_subset": [_p, _i64, _i32, _i64, _p, _i64, ctypes.c_int, _i32, _i32, _p, _p, _p, _p, _sz, _p],
-        "atsne_calibrate_p": [_p, _i64, _i32, _f32, _f32, _i32, _i32, _p, _p, _p, _p, _p],
+        "atsne_knn": [_p, _i64, _i32, _i64, ctypes.c_int, _i32, _i32, _p, _p, _p, _p, _p, _sz, _p],
+        "atsne_knn_subset": [_p, _i64, _i32, _i64, _p, _i64, ctypes.c_int, _i32, _i32, _p, _p, _p, _p, _p, _sz,
+                             _p],
+        "atsne_calibrate_p": [_p, _p, _i64, _i32, _f32, _f32, _i32, _i32, _p, _p, _p, _p, _p],
         "atsne_symmetrize_workspace_size": [_i64, _i64, _p],
         "atsne_symmetrize": [_p, _p, _i64, _i32, _p, _p, _p, _p, _p, _sz, _p],
         "atsne_symmetrize_csr": [_p, _p, _p, _i64, _i64, _p, _p, _p, _p, _p, _sz, _p],
@@ -142,8 +143,9 @@ def _dev(X: torch.Tensor, dtype, name):
 
 
 def knn(X: torch.Tensor, k: int, prec: str = "fp32", k_cand: int = 0, query_ids: torch.Tensor | None = None,
-        stream=None, workspace: torch.Tensor | None = None):
-    """Exact kNN (atsne_knn / atsne_knn_subset).  Returns (nbr_idx int32, nbr_d2 float32, flags uint8)."""
+        stream=None, workspace: torch.Tensor | None = None, d2_lo: torch.Tensor | None = None):
+    """Exact kNN (atsne_knn / atsne_knn_subset).  Returns (nbr_idx int32, nbr_d2 float32, flags uint8);
+    ``d2_lo`` (optional float32 [M, k] device tensor) receives the distances' residuals."""
     L = load()
     _dev(X, torch.float32, "X")
     if X.dim() != 2 or X.stride(1) != 1:
@@ -160,12 +162,17 @@ def knn(X: torch.Tensor, k: int, prec: str = "fp32", k_cand: int = 0, query_ids:
     idx = torch.empty((M, k), dtype=torch.int32, device=X.device)
     d2 = torch.empty((M, k), dtype=torch.float32, device=X.device)
     flags = torch.zeros((M,), dtype=torch.uint8, device=X.device)
+    if d2_lo is not None:
+        _dev(d2_lo, torch.float32, "d2_lo")
+        if tuple(d2_lo.shape) != (M, k) or not d2_lo.is_contiguous():
+            raise ValueError("d2_lo must be a contiguous [%d, %d] tensor" % (M, k))
     if query_ids is None:
-        _check(L.atsne_knn(_ptr(X), N, D, ld, PREC[prec], k, k_cand, _ptr(idx), _ptr(d2), _ptr(flags),
+        _check(L.atsne_knn(_ptr(X), N, D, ld, PREC[prec], k, k_cand, _ptr(idx), _ptr(d2), _ptr(d2_lo), _ptr(flags),
                            _ptr(workspace), workspace.numel(), _stream(stream)))
     else:
         _check(L.atsne_knn_subset(_ptr(X), N, D, ld, _ptr(query_ids), M, PREC[prec], k, k_cand, _ptr(idx),
-                                  _ptr(d2), _ptr(flags), _ptr(workspace), workspace.numel(), _stream(stream)))
+                                  _ptr(d2), _ptr(d2_lo), _ptr(flags), _ptr(workspace), workspace.numel(),
+                                  _stream(stream)))
     return idx, d2, flags
 
 
@@ -176,18 +183,24 @@ def knn_workspace_size(N: int, M: int, D: int, k: int, prec: str = "fp32", k_can
 
 
 def calibrate_p(nbr_d2: torch.Tensor, perplexity: float, tol: float = 0.0, max_iter: int = 0, strict: bool = False,
-                flags: torch.Tensor | None = None, stream=None):
-    """Perplexity bisection (atsne_calibrate_p).  Returns (P_cond, beta, perp, flags)."""
+                flags: torch.Tensor | None = None, stream=None, d2_lo: torch.Tensor | None = None):
+    """Perplexity bisection (atsne_calibrate_p).  Returns (P_cond, beta, perp, flags).  ``d2_lo``: the
+    distances' residuals from knn (optional)."""
     L = load()
     _dev(nbr_d2, torch.float32, "nbr_d2")
     nbr_d2 = nbr_d2.contiguous()
+    if d2_lo is not None:
+        _dev(d2_lo, torch.float32, "d2_lo")
+        d2_lo = d2_lo.contiguous()
+        if d2_lo.shape != nbr_d2.shape:
+            raise ValueError("d2_lo must match nbr_d2")
     N, k = nbr_d2.shape
     P = torch.empty_like(nbr_d2)
     beta = torch.empty((N,), dtype=torch.float32, device=nbr_d2.device)
     perp = torch.empty((N,), dtype=torch.float32, device=nbr_d2.device)
     if flags is None:
         flags = torch.zeros((N,), dtype=torch.uint8, device=nbr_d2.device)
-    _check(L.atsne_calibrate_p(_ptr(nbr_d2), N, k, float(perplexity), float(tol), int(max_iter), int(strict),
+    _check(L.atsne_calibrate_p(_ptr(nbr_d2), _ptr(d2_lo), N, k, float(perplexity), float(tol), int(max_iter), int(strict),
                                _ptr(P), _ptr(beta), _ptr(perp), _ptr(flags), _stream(stream)))
     return P, beta, perp, flags
 
@@ -234,8 +247,10 @@ def similarity(X: torch.Tensor, perplexity: float, prec: str = "fp32", k: int | 
     """kNN -> calibration -> symmetrisation, K = floor(3 mu) unless k is given."""
     if k is None:
         k = int(math.floor(3.0 * perplexity))
-    idx, d2, flags = knn(X, k, prec=prec, k_cand=k_cand, stream=stream)
-    P, beta, perp, flags = calibrate_p(d2, perplexity, flags=flags, stream=stream)
+    M = X.shape[0]
+    d2_lo = torch.empty((M, k), dtype=torch.float32, device=X.device)
+    idx, d2, flags = knn(X, k, prec=prec, k_cand=k_cand, stream=stream, d2_lo=d2_lo)
+    P, beta, perp, flags = calibrate_p(d2, perplexity, flags=flags, stream=stream, d2_lo=d2_lo)
     row_ptr, col, val = symmetrize(idx, P, stream=stream)
     return dict(idx=idx, d2=d2, flags=flags, P=P, beta=beta, perp=perp, row_ptr=row_ptr, col=col, val=val)
 

@@ -5,6 +5,11 @@
 // (Eq. 4) equals the target mu.  The entropy is taken in nats (2^{H_2} =
 // e^{H_e}) and the row is normalised over its neighbours, so it sums to one.
 //
+// Distances may come as unevaluated sums hi + lo (the kNN stage's residuals):
+// the shift delta_j = d_j - min d then resolves differences below FP32
+// resolution of d, which a row of close-together large distances needs for
+// its probabilities to be exact to 1e-6.
+//
 // One wavefront per row: each lane holds ceil(k/64) shifted distances in
 // registers; every bisection step costs one exponential per held distance
 // and two butterfly reductions (Z and sum w*delta).  H(beta) = ln Z +
@@ -23,9 +28,10 @@ constexpr int CAL_MAXR = 16;  // k <= 1024
 
 // Row r of the launch is table row (row_ids ? row_ids[r] : r); rows at or
 // beyond *n_rows_dev (when given) are skipped.  Distance and P rows have
-// stride `stride`.
+// stride `stride`; d2_lo (may be null) holds the distances' residuals.
 template <int R>
-__global__ __launch_bounds__(256) void calibrate_rows(const float* __restrict__ d2, int64_t stride,
+__global__ __launch_bounds__(256) void calibrate_rows(const float* __restrict__ d2, const float* __restrict__ d2_lo,
+                                                      int64_t stride,
                                                       const int32_t* __restrict__ row_ids,
                                                       const int32_t* __restrict__ n_rows_dev, int64_t N, int k,
                                                       float mu, float tol, int max_iter, float* __restrict__ P,
@@ -36,22 +42,32 @@ __global__ __launch_bounds__(256) void calibrate_rows(const float* __restrict__ 
     if (r_ >= N || (n_rows_dev && r_ >= *n_rows_dev)) return;
     const int64_t row = row_ids ? (int64_t)row_ids[r_] : r_;
     const float* d = d2 + row * stride;
-    float dl[R];
+    const float* dlo = d2_lo ? d2_lo + row * stride : nullptr;
+    float dl[R], dlw[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         int c = l + WAVE * r;
         dl[r] = c < k ? d[c] : INFINITY;
+        dlw[r] = (c < k && dlo) ? dlo[c] : 0.f;
     }
-    // +inf marks an absent entry (a deleted neighbour): weight 0
+    // +inf marks an absent entry (a deleted neighbour): weight 0.  The
+    // minimum is taken on (hi, lo) lexicographically; |lo| is at most about
+    // half an ulp of hi, so that is the minimum of hi + lo.
     float mn = INFINITY;
 #pragma unroll
     for (int r = 0; r < R; ++r) mn = fminf(mn, dl[r]);
     mn = wave_min(mn);
+    float mn_lo = INFINITY;
+#pragma unroll
+    for (int r = 0; r < R; ++r) mn_lo = dl[r] == mn ? fminf(mn_lo, dlw[r]) : mn_lo;
+    mn_lo = wave_min(mn_lo);
     float sum = 0.f, zeros = 0.f, live = 0.f;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         if (dl[r] < INFINITY) {
-            dl[r] -= mn;  // delta_j >= 0, min 0: Z >= 1, no overflow
+            // delta_j >= 0, min 0: Z >= 1, no overflow (hi - mn is exact
+            // whenever hi <= 2 mn; the residuals carry what FP32 drops)
+            dl[r] = fmaxf(0.f, (dl[r] - mn) + (dlw[r] - mn_lo));
             sum += dl[r];
             zeros += dl[r] == 0.f ? 1.f : 0.f;
             live += 1.f;
@@ -147,15 +163,15 @@ __global__ __launch_bounds__(256) void calibrate_rows(const float* __restrict__ 
     }
 }
 
-atsne_status calibrate_table(const float* d2, int64_t stride, const int32_t* row_ids, const int32_t* n_rows_dev,
-                             int64_t n_rows, int k, float mu, float tol, int max_iter, float* P, float* beta,
-                             float* perp, uint8_t* flags, hipStream_t st) {
+atsne_status calibrate_table(const float* d2, const float* d2_lo, int64_t stride, const int32_t* row_ids,
+                             const int32_t* n_rows_dev, int64_t n_rows, int k, float mu, float tol, int max_iter,
+                             float* P, float* beta, float* perp, uint8_t* flags, hipStream_t st) {
     if (n_rows == 0) return ATSNE_OK;
     const dim3 grid((unsigned)ceil_div(n_rows, 4)), block(256);
     const int R = (k + 63) / 64;
     ProfScope ps_("calibrate_rows", st);
 #define ATSNE_CAL(RR)                                                                                      \
-    calibrate_rows<RR><<<grid, block, 0, st>>>(d2, stride, row_ids, n_rows_dev, n_rows, k, mu, tol, max_iter, P, \
+    calibrate_rows<RR><<<grid, block, 0, st>>>(d2, d2_lo, stride, row_ids, n_rows_dev, n_rows, k, mu, tol, max_iter, P, \
                                                beta, perp, flags)
     if (R <= 1)
         ATSNE_CAL(1);
@@ -174,9 +190,9 @@ atsne_status calibrate_table(const float* d2, int64_t stride, const int32_t* row
 
 }  // namespace atsne
 
-extern "C" atsne_status atsne_calibrate_p(const float* nbr_d2, int64_t N, int32_t k, float perplexity, float tol,
-                                          int32_t max_iter, int32_t strict, float* P_cond, float* beta, float* perp,
-                                          uint8_t* flags, void* stream) {
+extern "C" atsne_status atsne_calibrate_p(const float* nbr_d2, const float* nbr_d2_lo, int64_t N, int32_t k,
+                                          float perplexity, float tol, int32_t max_iter, int32_t strict, float* P_cond,
+                                          float* beta, float* perp, uint8_t* flags, void* stream) {
     using namespace atsne;
     clear_error();
     ATSNE_REQUIRE(nbr_d2 && P_cond && beta, ATSNE_E_INVALID_ARG, "null input or output pointer");
@@ -189,8 +205,8 @@ extern "C" atsne_status atsne_calibrate_p(const float* nbr_d2, int64_t N, int32_
     if (max_iter <= 0) max_iter = 200;
     if (N == 0) return ATSNE_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    ATSNE_TRY(calibrate_table(nbr_d2, k, nullptr, nullptr, N, k, perplexity, tol, max_iter, P_cond, beta, perp, flags,
-                              st));
+    ATSNE_TRY(calibrate_table(nbr_d2, nbr_d2_lo, k, nullptr, nullptr, N, k, perplexity, tol, max_iter, P_cond, beta,
+                              perp, flags, st));
     if (strict) {
         std::vector<uint8_t> h((size_t)N);
         ATSNE_HIP(hipMemcpyAsync(h.data(), flags, (size_t)N, hipMemcpyDeviceToHost, st));

@@ -1038,10 +1038,12 @@ __global__ __launch_bounds__((TileGeom<P, SMALL>::THREADS)) __attribute__((amdgp
 constexpr float TIE_REL = 8e-6f;  // > worst-case relative error of the FP32 direct difference used here
 
 // Sort the n candidates (cj, cd) by the key (d, j) into sorted[0, n) by
-// counting ranks (keys are distinct).  Each lane ranks up to four candidates
-// in one pass over the keys, eight keys per step, so the LDS latency is paid
-// once per eight keys.  `tmp` is scratch for n keys.
-__device__ void rank_sort(int n, const int32_t* cj, const float* cd, uint64_t* tmp, uint64_t* sorted) {
+// counting ranks (keys are distinct); cdl (may be null) is the distances'
+// residuals, moved along into sorted_lo.  Each lane ranks up to four
+// candidates in one pass over the keys, eight keys per step, so the LDS
+// latency is paid once per eight keys.  `tmp` is scratch for n keys.
+__device__ void rank_sort(int n, const int32_t* cj, const float* cd, const float* cdl, uint64_t* tmp, uint64_t* sorted,
+                          float* sorted_lo) {
     const int l = lane_id();
     for (int c = l; c < n; c += WAVE) tmp[c] = pack_key(cd[c], cj[c]);
     wave_sync();
@@ -1071,16 +1073,22 @@ __device__ void rank_sort(int n, const int32_t* cj, const float* cd, uint64_t* t
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-            if (c0 + l + WAVE * u < n) sorted[r[u]] = kc[u];
+            if (c0 + l + WAVE * u < n) {
+                sorted[r[u]] = kc[u];
+                if (cdl) sorted_lo[r[u]] = cdl[c0 + l + WAVE * u];
+            }
     }
     wave_sync();
 }
 
 // Write the row from candidates already sorted by rank_sort: FP64 re-rank
-// when the k-th/(k+1)-th gap is below FP32 resolution.
+// when the k-th/(k+1)-th gap is below FP32 resolution.  out_d2_lo (may be
+// null) receives each distance's residual: sorted_lo's, or the FP64
+// distance's remainder after rounding to FP32 on the re-ranked rows.
 __device__ void finalize_sorted(const float* __restrict__ X, int64_t ld, int32_t D, const float* __restrict__ xq_g,
-                                int n, int k, const uint64_t* sorted, double* dd, int32_t* __restrict__ out_idx,
-                                float* __restrict__ out_d2, uint8_t* flag_out, uint8_t extra_flags) {
+                                int n, int k, const uint64_t* sorted, const float* sorted_lo, double* dd,
+                                int32_t* __restrict__ out_idx, float* __restrict__ out_d2,
+                                float* __restrict__ out_d2_lo, uint8_t* flag_out, uint8_t extra_flags) {
     const int l = lane_id();
     uint8_t fl = extra_flags;
     bool tie = false;
@@ -1164,8 +1172,10 @@ __device__ void finalize_sorted(const float* __restrict__ X, int64_t ld, int32_t
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 if (c0 + l + WAVE * u < n && r[u] < k) {
+                    const float h = (float)dc[u];
                     out_idx[r[u]] = jc[u];
-                    out_d2[r[u]] = (float)dc[u];
+                    out_d2[r[u]] = h;
+                    if (out_d2_lo) out_d2_lo[r[u]] = (float)(dc[u] - (double)h);
                 }
             }
         }
@@ -1174,6 +1184,7 @@ __device__ void finalize_sorted(const float* __restrict__ X, int64_t ld, int32_t
         for (int r = l; r < k; r += WAVE) {
             out_idx[r] = key_index(sorted[r]);
             out_d2[r] = key_dist(sorted[r]);
+            if (out_d2_lo) out_d2_lo[r] = sorted_lo ? sorted_lo[r] : 0.f;
         }
     }
     if (flag_out && l == 0) *flag_out = fl;
@@ -1181,25 +1192,32 @@ __device__ void finalize_sorted(const float* __restrict__ X, int64_t ld, int32_t
 
 // Sort the candidates (rank_sort, with dd as its scratch) and write the row.
 __device__ void finalize_row(const float* __restrict__ X, int64_t ld, int32_t D, const float* __restrict__ xq_g,
-                             int n, int k, int32_t* cj, float* cd, uint64_t* sorted, double* dd,
-                             int32_t* __restrict__ out_idx, float* __restrict__ out_d2, uint8_t* flag_out,
-                             uint8_t extra_flags) {
-    rank_sort(n, cj, cd, reinterpret_cast<uint64_t*>(dd), sorted);
-    finalize_sorted(X, ld, D, xq_g, n, k, sorted, dd, out_idx, out_d2, flag_out, extra_flags);
+                             int n, int k, int32_t* cj, float* cd, float* cdl, uint64_t* sorted, float* sorted_lo,
+                             double* dd, int32_t* __restrict__ out_idx, float* __restrict__ out_d2,
+                             float* __restrict__ out_d2_lo, uint8_t* flag_out, uint8_t extra_flags) {
+    rank_sort(n, cj, cd, cdl, reinterpret_cast<uint64_t*>(dd), sorted, sorted_lo);
+    finalize_sorted(X, ld, D, xq_g, n, k, sorted, sorted_lo, dd, out_idx, out_d2, out_d2_lo, flag_out, extra_flags);
 }
 
-// Exact FP32 direct-difference squared distances |x_q - x_j|^2 for G rows at
-// once, in the one summation order every kernel that reports a distance
-// uses: lane l accumulates the elements d = l, l + 64, ... in increasing
-// order with one fma each, and the 64 lane partials are then added by a
-// butterfly.  The G rows' loads are in flight together; every lane
-// receives the G sums.
+// FP32 direct-difference squared distances |x_q - x_j|^2 for G rows at
+// once, each as an unevaluated sum hi + lo: hi is the distance rounded to
+// FP32 and lo its residual.  Every kernel that reports a distance uses this
+// one summation order: lane l accumulates the elements d = l, l + 64, ... in
+// increasing order with one fma each (direct_partials), and the 64 lane
+// partials are then added pairwise over the lane-index bits 5, 4, ..., 0 by
+// TwoSums whose rounding errors are collected apart; hi, lo = Fast2Sum(sum,
+// errors).  The six levels of additions of ever larger partials are where a
+// plain FP32 sum loses most of its accuracy; with them compensated, hi + lo
+// is within a few hundredths of an ulp of the distance on the image-like
+// workload, so distance differences are resolved below FP32 resolution,
+// which the perplexity calibration needs when a row's distances are close
+// together relative to their size.  The G rows' loads are in flight together.
 template <int G>
-__device__ __forceinline__ void direct_group(const float* __restrict__ xq, const float* const (&xr)[G], int32_t D,
-                                             float (&out)[G]) {
+__device__ __forceinline__ void direct_partials(const float* __restrict__ xq, const float* const (&xr)[G], int32_t D,
+                                                float (&s)[G]) {
     const int l = lane_id();
 #pragma unroll
-    for (int e = 0; e < G; ++e) out[e] = 0.f;
+    for (int e = 0; e < G; ++e) s[e] = 0.f;
     for (int d = l; d < D; d += WAVE) {
         const float q = xq[d];
         float xv[G];
@@ -1208,29 +1226,85 @@ __device__ __forceinline__ void direct_group(const float* __restrict__ xq, const
 #pragma unroll
         for (int e = 0; e < G; ++e) {
             const float t = q - xv[e];
-            out[e] = fmaf(t, t, out[e]);
+            s[e] = fmaf(t, t, s[e]);
+        }
+    }
+}
+
+// One pairwise level of the compensated reduction: (s, c) of this lane and
+// of lane l ^ o.
+__device__ __forceinline__ void comp_level(float& s, float& c, float s2, float c2) {
+    float se;
+    s = two_sum(s, s2, se);
+    c = (c + c2) + se;
+}
+
+// Every lane receives the G pairs (hi, lo).
+template <int G>
+__device__ __forceinline__ void direct_group(const float* __restrict__ xq, const float* const (&xr)[G], int32_t D,
+                                             float (&hi)[G], float (&lo)[G]) {
+    float s[G], c[G];
+    direct_partials<G>(xq, xr, D, s);
+#pragma unroll
+    for (int e = 0; e < G; ++e) c[e] = 0.f;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+#pragma unroll
+        for (int e = 0; e < G; ++e) comp_level(s[e], c[e], __shfl_xor(s[e], o, WAVE), __shfl_xor(c[e], o, WAVE));
+    }
+#pragma unroll
+    for (int e = 0; e < G; ++e) {
+        hi[e] = s[e] + c[e];
+        lo[e] = c[e] - (hi[e] - s[e]);
+    }
+}
+
+// The same sums for 16 rows, reduce-scattered: at the levels over lane bits
+// 5..2 a lane keeps half of its remaining rows and sends the other half to
+// its partner, so each level adds exactly the pairs the full reduction adds
+// (identical results) at a quarter of its exchanges.  Lane l ends with row
+// e(l) = 8 b5 + 4 b4 + 2 b3 + b2 (b_i = bit i of l); returns e(l).
+__device__ __forceinline__ int direct_group16_scatter(const float* __restrict__ xq, const float* const (&xr)[16],
+                                                      int32_t D, float& hi, float& lo) {
+    const int l = lane_id();
+    float s[16], c[16];
+    direct_partials<16>(xq, xr, D, s);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) c[e] = 0.f;
+#pragma unroll
+    for (int h = 8, o = 32; h >= 1; h >>= 1, o >>= 1) {
+        const bool upper = (l & o) != 0;
+#pragma unroll
+        for (int i = 0; i < h; ++i) {
+            const float ks = upper ? s[i + h] : s[i], kc = upper ? c[i + h] : c[i];
+            const float ts = upper ? s[i] : s[i + h], tc = upper ? c[i] : c[i + h];
+            s[i] = ks;
+            c[i] = kc;
+            comp_level(s[i], c[i], __shfl_xor(ts, o, WAVE), __shfl_xor(tc, o, WAVE));
         }
     }
 #pragma unroll
-    for (int e = 0; e < G; ++e) out[e] = wave_sum(out[e]);
+    for (int o = 2; o >= 1; o >>= 1) comp_level(s[0], c[0], __shfl_xor(s[0], o, WAVE), __shfl_xor(c[0], o, WAVE));
+    hi = s[0] + c[0];
+    lo = c[0] - (hi - s[0]);
+    return 8 * ((l >> 5) & 1) + 4 * ((l >> 4) & 1) + 2 * ((l >> 3) & 1) + ((l >> 2) & 1);
 }
 
-// Exact FP32 direct-difference distances from query xq to the n candidates
-// in cj, into cd, sixteen candidates at a time (a short last group repeats
-// its last candidate and drops the copies).
+// Direct-difference distances from query xq to the n candidates in cj, into
+// cd (hi) and cdl (lo, may be null), sixteen candidates at a time (a short
+// last group repeats its last candidate and drops the copies).
 __device__ void direct_distances(const float* __restrict__ X, int64_t ld, int32_t D, const float* __restrict__ xq,
-                                 int n, const int32_t* cj, float* cd) {
+                                 int n, const int32_t* cj, float* cd, float* cdl) {
     const int l = lane_id();
     for (int c = 0; c < n; c += 16) {
         const float* xr[16];
 #pragma unroll
         for (int e = 0; e < 16; ++e) xr[e] = X + (int64_t)cj[min(c + e, n - 1)] * ld;
-        float acc[16];
-        direct_group<16>(xq, xr, D, acc);
-        if (l == 0) {
-#pragma unroll
-            for (int e = 0; e < 16; ++e)
-                if (c + e < n) cd[c + e] = acc[e];
+        float hi, lo;
+        const int e = direct_group16_scatter(xq, xr, D, hi, lo);
+        if ((l & 3) == 0 && c + e < n) {
+            cd[c + e] = hi;
+            if (cdl) cdl[c + e] = lo;
         }
     }
     wave_sync();
@@ -1265,6 +1339,7 @@ struct SelArgs {
     const int32_t* counts;
     int32_t* out_idx;
     float* out_d2;
+    float* out_d2_lo;  // may be null
     uint8_t* out_flags;
     int64_t out_stride;
     int32_t* scan_list;
@@ -1293,7 +1368,7 @@ constexpr int SEL_MAX_S = 64;  // splits whose prefix counts fit the LDS table
 
 // LDS of knn_select for up to kcap candidates (sized at launch).
 __host__ __device__ constexpr size_t select_lds_bytes(int kcap) {
-    return (256 * 4 + (size_t)kcap * (8 + 8 + 4 + 4) + 16 + 15) & ~(size_t)15;
+    return (256 * 4 + (size_t)kcap * (8 + 8 + 4 + 4 + 4 + 4) + 16 + 15) & ~(size_t)15;
 }
 constexpr int SEL_ROWS = 4;  // at most this many rows (one wave each) per workgroup
 // rows per workgroup for a candidate capacity: keep the dynamic LDS within 64 KiB
@@ -1311,7 +1386,9 @@ __global__ __launch_bounds__(64 * SEL_ROWS) void knn_select(SelArgs a, int kcap)
     uint32_t* hist = reinterpret_cast<uint32_t*>(sorted + kcap);
     int32_t* cj = reinterpret_cast<int32_t*>(hist + 256);
     float* cd = reinterpret_cast<float*>(cj + kcap);
-    int32_t& ncand = *reinterpret_cast<int32_t*>(cd + kcap);
+    float* cdl = cd + kcap;
+    float* sorted_lo = cdl + kcap;
+    int32_t& ncand = *reinterpret_cast<int32_t*>(sorted_lo + kcap);
     const int l = lane_id();
     const int64_t m = (int64_t)blockIdx.x * (blockDim.x >> 6) + w;
     if (m >= a.M) return;  // waves are independent: no workgroup barrier below
@@ -1323,6 +1400,7 @@ __global__ __launch_bounds__(64 * SEL_ROWS) void knn_select(SelArgs a, int kcap)
     const uint64_t* base = a.slots + (size_t)m * a.S * (size_t)a.cap;
     int32_t* out_idx = a.out_idx + m * a.out_stride;
     float* out_d2 = a.out_d2 + m * a.out_stride;
+    float* out_d2_lo = a.out_d2_lo ? a.out_d2_lo + m * a.out_stride : nullptr;
 
     // with deletion stamps, slots can still hold keys of rows deleted before
     // the row's view (those appended after the slot's last shrink): skip them
@@ -1416,10 +1494,10 @@ __global__ __launch_bounds__(64 * SEL_ROWS) void knn_select(SelArgs a, int kcap)
     // FP64 re-rank and the certificate are therefore those of all n.
     int ne = n;
     if ((P == ATSNE_PREC_FP32 || P == ATSNE_PREC_FP32X3) && a.norms && a.pmax && n > k + 1) {
-        rank_sort(n, cj, cd, reinterpret_cast<uint64_t*>(dd), sorted);  // by (d', j)
+        rank_sort(n, cj, cd, nullptr, reinterpret_cast<uint64_t*>(dd), sorted, nullptr);  // by (d', j)
         for (int c = l; c < n; c += WAVE) cj[c] = key_index(sorted[c]);
         wave_sync();
-        direct_distances(a.X, a.ld, a.D, xq, k + 1, cj, cd);
+        direct_distances(a.X, a.ld, a.D, xq, k + 1, cj, cd, cdl);
         float mx = 0.0f;
         for (int c = l; c < k + 1; c += WAVE) mx = fmaxf(mx, cd[c]);
         const float cap = wave_max(mx) * (1.0f + 4.0f * TIE_REL);
@@ -1437,19 +1515,20 @@ __global__ __launch_bounds__(64 * SEL_ROWS) void knn_select(SelArgs a, int kcap)
             if (bm) last = c0 + 63 - __clzll(bm);
         }
         ne = last + 1;
-        direct_distances(a.X, a.ld, a.D, xq, ne - (k + 1), cj + k + 1, cd + k + 1);
+        direct_distances(a.X, a.ld, a.D, xq, ne - (k + 1), cj + k + 1, cd + k + 1, cdl + k + 1);
     } else {
-        direct_distances(a.X, a.ld, a.D, xq, n, cj, cd);
+        direct_distances(a.X, a.ld, a.D, xq, n, cj, cd, cdl);
     }
     if (n < k) {  // fewer keys than requested neighbours (caller error): pad
         for (int r = l; r < k; r += WAVE) {
             out_idx[r] = -1;
             out_d2[r] = INFINITY;
+            if (out_d2_lo) out_d2_lo[r] = 0.f;
         }
     }
 
     uint8_t extra = 0;
-    if (n >= k) rank_sort(ne, cj, cd, reinterpret_cast<uint64_t*>(dd), sorted);
+    if (n >= k) rank_sort(ne, cj, cd, cdl, reinterpret_cast<uint64_t*>(dd), sorted, sorted_lo);
     const int64_t n_valid = max<int64_t>(0, nl - a.key_lo) - ((q >= a.key_lo && q < nl) ? 1 : 0);
     if ((P == ATSNE_PREC_FP32 || P == ATSNE_PREC_FP32X3) && take < n_valid && n >= k) {
         // Certificate: every non-candidate j has d'_j >= d'(kstar), so its
@@ -1471,7 +1550,7 @@ __global__ __launch_bounds__(64 * SEL_ROWS) void knn_select(SelArgs a, int kcap)
         }
     }
     if (n >= k)
-        finalize_sorted(a.X, a.ld, a.D, xq, ne, k, sorted, dd, out_idx, out_d2,
+        finalize_sorted(a.X, a.ld, a.D, xq, ne, k, sorted, sorted_lo, dd, out_idx, out_d2, out_d2_lo,
                         a.out_flags ? a.out_flags + m : nullptr, extra);
 }
 
@@ -1490,7 +1569,9 @@ __global__ __launch_bounds__(256) void knn_scan(SelArgs a, int keep_extra, int32
     __shared__ int32_t rcount[4];
     __shared__ int32_t cj[MAX_KC];
     __shared__ float cd[MAX_KC];
+    __shared__ float cdl[MAX_KC];
     __shared__ uint64_t sorted[MAX_KC];
+    __shared__ float sorted_lo[MAX_KC];
     __shared__ double dd[MAX_KC];
     __shared__ int32_t item;
     const int t = threadIdx.x, l = t & 63, w = t >> 6;
@@ -1511,6 +1592,7 @@ __global__ __launch_bounds__(256) void knn_scan(SelArgs a, int keep_extra, int32
         const int keep = min(k + keep_extra, SCAN_REGION - 24);
         int32_t* out_idx = a.out_idx + m * a.out_stride;
         float* out_d2 = a.out_d2 + m * a.out_stride;
+        float* out_d2_lo = a.out_d2_lo ? a.out_d2_lo + m * a.out_stride : nullptr;
         const float* xq = a.X + q * a.ld;
         // The current k-th exact distance bounds the true k-th from above;
         // widened by the near-tie band, so the keys just past the k-th (which
@@ -1535,8 +1617,8 @@ __global__ __launch_bounds__(256) void knn_scan(SelArgs a, int keep_extra, int32
             const float* xr[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) xr[u] = a.X + (j0 + 4 * u < r_hi ? j0 + 4 * u : j0) * a.ld;
-            float dj[4];
-            direct_group<4>(xq, xr, a.D, dj);
+            float dj[4], dj_lo[4];
+            direct_group<4>(xq, xr, a.D, dj, dj_lo);
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int64_t j = j0 + 4 * u;
@@ -1598,9 +1680,13 @@ __global__ __launch_bounds__(256) void knn_scan(SelArgs a, int keep_extra, int32
                 }
             }
             wave_sync();
+            // the residuals of the chosen candidates (their distances are
+            // recomputed by the same arithmetic, so hi equals the key's)
+            if (out_d2_lo) direct_distances(a.X, a.ld, a.D, xq, n, cj, cd, cdl);
             if (n >= k)
-                finalize_row(a.X, a.ld, a.D, xq, n, k, cj, cd, sorted, dd, out_idx, out_d2,
-                             a.out_flags ? a.out_flags + m : nullptr, ATSNE_FLAG_EXACT_SCAN);
+                finalize_row(a.X, a.ld, a.D, xq, n, k, cj, cd, out_d2_lo ? cdl : nullptr, sorted, sorted_lo, dd,
+                             out_idx, out_d2, out_d2_lo, a.out_flags ? a.out_flags + m : nullptr,
+                             ATSNE_FLAG_EXACT_SCAN);
         }
     }
 }
@@ -1616,6 +1702,7 @@ struct RevArgs {
     SelArgs s;
     int32_t* res_idx;
     float* res_d2;
+    float* res_d2_lo;  // may be null
     uint8_t* res_flags;
     int64_t res_stride;
     int32_t* changed;
@@ -1626,7 +1713,9 @@ __global__ __launch_bounds__(64) void knn_reverse_merge(RevArgs r) {
     __shared__ uint32_t hist[256];
     __shared__ int32_t cj[MAX_KC];
     __shared__ float cd[MAX_KC];
+    __shared__ float cdl[MAX_KC];
     __shared__ uint64_t sorted[MAX_KC];
+    __shared__ float sorted_lo[MAX_KC];
     __shared__ double dd[MAX_KC];
     __shared__ int32_t ncand;
     const SelArgs& a = r.s;
@@ -1652,6 +1741,7 @@ __global__ __launch_bounds__(64) void knn_reverse_merge(RevArgs r) {
     const uint64_t kstar = union_threshold(each, take, total, hist);
     int32_t* ridx = r.res_idx + q * r.res_stride;
     float* rd2 = r.res_d2 + q * r.res_stride;
+    float* rd2_lo = r.res_d2_lo ? r.res_d2_lo + q * r.res_stride : nullptr;
     int np = 0;
     for (int i0 = 0; i0 < k; i0 += WAVE) np += __popcll(ballot(i0 + l < k && ridx[i0 + l] >= 0));
     if (np == 0) return;
@@ -1666,7 +1756,7 @@ __global__ __launch_bounds__(64) void knn_reverse_merge(RevArgs r) {
     wave_sync();
     const int nc = ncand;
     const float* xq = a.X + q * a.ld;
-    direct_distances(a.X, a.ld, a.D, xq, nc, cj + k, cd + k);
+    direct_distances(a.X, a.ld, a.D, xq, nc, cj + k, cd + k, cdl + k);
     const float dmax = rd2[np - 1];
     // keep the new keys strictly closer than the farthest present neighbour
     int c = 0;
@@ -1675,12 +1765,14 @@ __global__ __launch_bounds__(64) void knn_reverse_merge(RevArgs r) {
         const bool kp = i < nc && cd[k + i] < dmax;
         int32_t jj = kp ? cj[k + i] : 0;
         float dv = kp ? cd[k + i] : 0.f;
+        float dvl = kp ? cdl[k + i] : 0.f;
         const uint64_t mm = ballot(kp);
         wave_sync();
         if (kp) {
             const int p = c + __popcll(mm & lanemask_lt());
             cj[k + p] = jj;
             cd[k + p] = dv;
+            cdl[k + p] = dvl;
         }
         c += __popcll(mm);
         wave_sync();
@@ -1693,10 +1785,12 @@ __global__ __launch_bounds__(64) void knn_reverse_merge(RevArgs r) {
             const int i = i0 + l;
             const int32_t jj = i < c ? cj[k + i] : 0;
             const float dv = i < c ? cd[k + i] : 0.f;
+            const float dvl = i < c ? cdl[k + i] : 0.f;
             wave_sync();
             if (i < c) {
                 cj[np + i] = jj;
                 cd[np + i] = dv;
+                cdl[np + i] = dvl;
             }
             wave_sync();
         }
@@ -1704,9 +1798,10 @@ __global__ __launch_bounds__(64) void knn_reverse_merge(RevArgs r) {
     for (int i = l; i < np; i += WAVE) {
         cj[i] = ridx[i];
         cd[i] = rd2[i];
+        cdl[i] = rd2_lo ? rd2_lo[i] : 0.f;
     }
     wave_sync();
-    finalize_row(a.X, a.ld, a.D, xq, np + c, np, cj, cd, sorted, dd, ridx, rd2,
+    finalize_row(a.X, a.ld, a.D, xq, np + c, np, cj, cd, cdl, sorted, sorted_lo, dd, ridx, rd2, rd2_lo,
                  r.res_flags ? r.res_flags + q : nullptr, 0);
     if (l == 0) {
         const int p = atomicAdd(r.n_changed, 1);
@@ -2043,6 +2138,7 @@ static SelArgs sel_args(const Corpus& c, const Batch& b, const SearchPlan& p, co
     s.counts = w.counts;
     s.out_idx = b.out_idx;
     s.out_d2 = b.out_d2;
+    s.out_d2_lo = b.out_d2_lo;
     s.out_flags = b.out_flags;
     s.out_stride = b.out_stride;
     s.scan_list = w.scan_list;
@@ -2088,8 +2184,8 @@ atsne_status knn_search(const Corpus& c, const Batch& b, const SearchPlan& p, vo
 }
 
 atsne_status knn_reverse(const Corpus& c, const Batch& b, const SearchPlan& p, int32_t* res_idx, float* res_d2,
-                         uint8_t* res_flags, int64_t res_stride, int32_t* changed, int32_t* n_changed, void* ws,
-                         hipStream_t st) {
+                         float* res_d2_lo, uint8_t* res_flags, int64_t res_stride, int32_t* changed,
+                         int32_t* n_changed, void* ws, hipStream_t st) {
     if (b.M == 0) return ATSNE_OK;
     ATSNE_REQUIRE(c.prec == ATSNE_PREC_FP32 || c.prec == ATSNE_PREC_FP32X3, ATSNE_E_UNSUPPORTED,
                   "reverse merge needs an exact contraction (FP32 or FP32X3 corpus)");
@@ -2100,6 +2196,7 @@ atsne_status knn_reverse(const Corpus& c, const Batch& b, const SearchPlan& p, i
     r.s = sel_args(c, b, p, w);
     r.res_idx = res_idx;
     r.res_d2 = res_d2;
+    r.res_d2_lo = res_d2_lo;
     r.res_flags = res_flags;
     r.res_stride = res_stride;
     r.changed = changed;
@@ -2165,7 +2262,7 @@ static atsne_status make_plan(int64_t N, int64_t M, int32_t D, int prec, int k, 
 
 static atsne_status knn_impl(const float* X, int64_t N, int32_t D, int64_t ld, const int32_t* qids, int64_t M,
                              atsne_precision prec, int32_t k, int32_t k_cand, int32_t* nbr_idx, float* nbr_d2,
-                             uint8_t* flags, void* ws, size_t ws_bytes, void* stream) {
+                             float* nbr_d2_lo, uint8_t* flags, void* ws, size_t ws_bytes, void* stream) {
     clear_error();
     ATSNE_REQUIRE(X && nbr_idx && nbr_d2, ATSNE_E_INVALID_ARG, "null X or output pointer");
     ATSNE_REQUIRE(ld >= D, ATSNE_E_INVALID_ARG, "ld=%lld < D=%d", (long long)ld, D);
@@ -2190,6 +2287,7 @@ static atsne_status knn_impl(const float* X, int64_t N, int32_t D, int64_t ld, c
         b.kc = p.kc;
         b.out_idx = nbr_idx + m0 * k;
         b.out_d2 = nbr_d2 + m0 * k;
+        b.out_d2_lo = nbr_d2_lo ? nbr_d2_lo + m0 * k : nullptr;
         b.out_flags = flags ? flags + m0 : nullptr;
         b.out_stride = k;
         ATSNE_TRY(knn_search(c, b, p.sp, sws, st));
@@ -2210,14 +2308,17 @@ extern "C" atsne_status atsne_knn_workspace_size(int64_t N, int64_t M, int32_t D
 }
 
 extern "C" atsne_status atsne_knn(const float* X, int64_t N, int32_t D, int64_t ld, atsne_precision prec, int32_t k,
-                                  int32_t k_cand, int32_t* nbr_idx, float* nbr_d2, uint8_t* flags, void* ws,
-                                  size_t ws_bytes, void* stream) {
-    return atsne::knn_impl(X, N, D, ld, nullptr, N, prec, k, k_cand, nbr_idx, nbr_d2, flags, ws, ws_bytes, stream);
+                                  int32_t k_cand, int32_t* nbr_idx, float* nbr_d2, float* nbr_d2_lo, uint8_t* flags,
+                                  void* ws, size_t ws_bytes, void* stream) {
+    return atsne::knn_impl(X, N, D, ld, nullptr, N, prec, k, k_cand, nbr_idx, nbr_d2, nbr_d2_lo, flags, ws, ws_bytes,
+                           stream);
 }
 
 extern "C" atsne_status atsne_knn_subset(const float* X, int64_t N, int32_t D, int64_t ld, const int32_t* query_ids,
                                          int64_t M, atsne_precision prec, int32_t k, int32_t k_cand, int32_t* nbr_idx,
-                                         float* nbr_d2, uint8_t* flags, void* ws, size_t ws_bytes, void* stream) {
+                                         float* nbr_d2, float* nbr_d2_lo, uint8_t* flags, void* ws, size_t ws_bytes,
+                                         void* stream) {
     ATSNE_REQUIRE(query_ids || M == 0, ATSNE_E_INVALID_ARG, "null query_ids");
-    return atsne::knn_impl(X, N, D, ld, query_ids, M, prec, k, k_cand, nbr_idx, nbr_d2, flags, ws, ws_bytes, stream);
+    return atsne::knn_impl(X, N, D, ld, query_ids, M, prec, k, k_cand, nbr_idx, nbr_d2, nbr_d2_lo, flags, ws,
+                           ws_bytes, stream);
 }

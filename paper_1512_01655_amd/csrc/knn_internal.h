@@ -63,6 +63,7 @@ struct Batch {
     const int32_t* row_blk = nullptr;
     int32_t* out_idx = nullptr;
     float* out_d2 = nullptr;
+    float* out_d2_lo = nullptr;  // residuals of out_d2 (may be null)
     uint8_t* out_flags = nullptr;
     int64_t out_stride = 0;
 };
@@ -98,14 +99,15 @@ atsne_status knn_search(const Corpus& c, const Batch& b, const SearchPlan& p, vo
 // resident row's farthest neighbour enters its list, evicting the farthest;
 // ids of changed rows are appended to changed[*n_changed].
 atsne_status knn_reverse(const Corpus& c, const Batch& b, const SearchPlan& p, int32_t* res_idx, float* res_d2,
-                         uint8_t* res_flags, int64_t res_stride, int32_t* changed, int32_t* n_changed, void* ws,
-                         hipStream_t st);
+                         float* res_d2_lo, uint8_t* res_flags, int64_t res_stride, int32_t* changed,
+                         int32_t* n_changed, void* ws, hipStream_t st);
 
 // Calibrate rows of a neighbour table in place: row r is table row
-// (row_ids ? row_ids[r] : r); d2/P rows have stride `stride`, k entries.
-atsne_status calibrate_table(const float* d2, int64_t stride, const int32_t* row_ids, const int32_t* n_rows_dev,
-                             int64_t n_rows, int k, float mu, float tol, int max_iter, float* P, float* beta,
-                             float* perp, uint8_t* flags, hipStream_t st);
+// (row_ids ? row_ids[r] : r); d2/P rows have stride `stride`, k entries;
+// d2_lo (may be null) holds the distances' residuals.
+atsne_status calibrate_table(const float* d2, const float* d2_lo, int64_t stride, const int32_t* row_ids,
+                             const int32_t* n_rows_dev, int64_t n_rows, int k, float mu, float tol, int max_iter,
+                             float* P, float* beta, float* perp, uint8_t* flags, hipStream_t st);
 
 // Ascending 64-bit key sort (radix); tmp holds sort_u64_temp_bytes(n) bytes.
 size_t sort_u64_temp_bytes(int64_t n);
@@ -119,9 +121,9 @@ SearchPlan plan_list_search(int64_t M, int64_t n_blocks, int k_max, int kc_max, 
 // per row, present entries first, absent ones (index -1, +inf) last.
 atsne_status serve_fill_death(int32_t* death, int64_t n, hipStream_t st);
 atsne_status serve_mark_deleted(int32_t* death, const int32_t* ids, int64_t M, int32_t c, hipStream_t st);
-atsne_status serve_purge_deleted(int32_t* res_idx, float* res_d2, float* res_P, float* res_beta, uint8_t* res_flags,
-                                 int k, int64_t n_rows, const int32_t* death, int32_t c, int32_t* changed,
-                                 int32_t* n_changed, hipStream_t st);
+atsne_status serve_purge_deleted(int32_t* res_idx, float* res_d2, float* res_d2_lo, float* res_P, float* res_beta,
+                                 uint8_t* res_flags, int k, int64_t n_rows, const int32_t* death, int32_t c,
+                                 int32_t* changed, int32_t* n_changed, hipStream_t st);
 atsne_status serve_farthest(const int32_t* res_idx, const float* res_d2, int k, int64_t n_rows, float* dmax,
                             hipStream_t st);
 atsne_status serve_state(const int32_t* res_idx, int k, int64_t n_rows, const int32_t* death, float* rho,

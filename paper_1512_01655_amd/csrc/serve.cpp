@@ -121,6 +121,7 @@ struct Request {
     int32_t* row_ids = nullptr;
     int32_t* nbr_idx = nullptr;
     float* nbr_d2 = nullptr;
+    float* nbr_d2_lo = nullptr;  // residuals of nbr_d2 (calibration input)
     float* P = nullptr;
     float* beta = nullptr;
     uint8_t* flags = nullptr;
@@ -151,6 +152,7 @@ struct BatchSlot {
     int32_t* h_desc = nullptr;  // pinned staging
     int32_t* b_idx = nullptr;
     float* b_d2 = nullptr;
+    float* b_d2_lo = nullptr;
     uint8_t* b_flags = nullptr;
 };
 
@@ -173,6 +175,7 @@ struct atsne_server {
     void* corpus_mem = nullptr;
     int32_t* res_idx = nullptr;
     float* res_d2 = nullptr;
+    float* res_d2_lo = nullptr;  // residuals of res_d2 (calibration input)
     float* res_P = nullptr;
     float* res_beta = nullptr;
     uint8_t* res_flags = nullptr;
@@ -224,6 +227,7 @@ size_t request_bytes(const Request& r) {
     a.take<int32_t>(r.n * r.k);
     a.take<float>(r.n * r.k);
     a.take<float>(r.n * r.k);
+    a.take<float>(r.n * r.k);
     a.take<float>(r.n);
     a.take<uint8_t>(r.n);
     if (r.kind != 1) {
@@ -238,6 +242,7 @@ void carve_request(Request& r) {
     r.row_ids = a.take<int32_t>(r.n);
     r.nbr_idx = a.take<int32_t>(r.n * r.k);
     r.nbr_d2 = a.take<float>(r.n * r.k);
+    r.nbr_d2_lo = a.take<float>(r.n * r.k);
     r.P = a.take<float>(r.n * r.k);
     r.beta = a.take<float>(r.n);
     r.flags = a.take<uint8_t>(r.n);
@@ -291,6 +296,7 @@ atsne_status launch_batch(atsne_server* s, BatchSlot& b, const std::vector<Seg>&
     bt.key_lo = 0;
     bt.out_idx = b.b_idx;
     bt.out_d2 = b.b_d2;
+    bt.out_d2_lo = b.b_d2_lo;
     bt.out_flags = b.b_flags;
     bt.out_stride = s->kmax;
     ATSNE_TRY(knn_search(s->corpus, bt, p, b.ws, b.st));
@@ -300,6 +306,8 @@ atsne_status launch_batch(atsne_server* s, BatchSlot& b, const std::vector<Seg>&
                                    g.n, hipMemcpyDeviceToDevice, b.st));
         ATSNE_HIP(hipMemcpy2DAsync(g.r->nbr_d2 + g.r0 * k, k * 4, b.b_d2 + g.b0 * s->kmax, s->kmax * 4, k * 4, g.n,
                                    hipMemcpyDeviceToDevice, b.st));
+        ATSNE_HIP(hipMemcpy2DAsync(g.r->nbr_d2_lo + g.r0 * k, k * 4, b.b_d2_lo + g.b0 * s->kmax, s->kmax * 4, k * 4,
+                                   g.n, hipMemcpyDeviceToDevice, b.st));
         ATSNE_HIP(hipMemcpyAsync(g.r->flags + g.r0, b.b_flags + g.b0, g.n, hipMemcpyDeviceToDevice, b.st));
     }
     ATSNE_HIP(hipEventRecord(b.ev, b.st));
@@ -308,7 +316,7 @@ atsne_status launch_batch(atsne_server* s, BatchSlot& b, const std::vector<Seg>&
 
 // Finish a refine: calibrate its rows at its own perplexity.
 atsne_status finish_refine(atsne_server* s, Request& r) {
-    ATSNE_TRY(calibrate_table(r.nbr_d2, r.k, nullptr, nullptr, r.n, r.k, r.mu, 1e-5f, 200, r.P, r.beta, nullptr,
+    ATSNE_TRY(calibrate_table(r.nbr_d2, r.nbr_d2_lo, r.k, nullptr, nullptr, r.n, r.k, r.mu, 1e-5f, 200, r.P, r.beta, nullptr,
                               r.flags, s->s_finish));
     ATSNE_HIP(hipEventRecord(r.fin, s->s_finish));
     return ATSNE_OK;
@@ -322,8 +330,9 @@ atsne_status commit_insert(atsne_server* s, Request& r) {
     // 1. the new rows' exact lists enter the resident table and are calibrated
     ATSNE_HIP(hipMemcpyAsync(s->res_idx + r0 * K, r.nbr_idx, sizeof(int32_t) * B * K, hipMemcpyDeviceToDevice, st));
     ATSNE_HIP(hipMemcpyAsync(s->res_d2 + r0 * K, r.nbr_d2, sizeof(float) * B * K, hipMemcpyDeviceToDevice, st));
+    ATSNE_HIP(hipMemcpyAsync(s->res_d2_lo + r0 * K, r.nbr_d2_lo, sizeof(float) * B * K, hipMemcpyDeviceToDevice, st));
     ATSNE_HIP(hipMemcpyAsync(s->res_flags + r0, r.flags, B, hipMemcpyDeviceToDevice, st));
-    ATSNE_TRY(calibrate_table(s->res_d2 + r0 * K, K, nullptr, nullptr, B, K, s->mu0, 1e-5f, 200, s->res_P + r0 * K,
+    ATSNE_TRY(calibrate_table(s->res_d2 + r0 * K, s->res_d2_lo + r0 * K, K, nullptr, nullptr, B, K, s->mu0, 1e-5f, 200, s->res_P + r0 * K,
                               s->res_beta + r0, nullptr, s->res_flags + r0, st));
     // 2. Eq. 13 over the residents that existed before this insert; the
     // threshold of a row is its farthest present neighbour
@@ -343,10 +352,10 @@ atsne_status commit_insert(atsne_server* s, Request& r) {
         bt.tau0 = s->res_dmax;
         bt.tau0_stride = 1;
         bt.view = (int32_t)r.epoch;
-        ATSNE_TRY(knn_reverse(s->corpus, bt, p, s->res_idx, s->res_d2, s->res_flags, K, r.changed, r.n_changed_dev,
+        ATSNE_TRY(knn_reverse(s->corpus, bt, p, s->res_idx, s->res_d2, s->res_d2_lo, s->res_flags, K, r.changed, r.n_changed_dev,
                               s->rev_ws, st));
         // 3. re-calibrate the changed rows in place (count stays on the device)
-        ATSNE_TRY(calibrate_table(s->res_d2, K, r.changed, r.n_changed_dev, r0, K, s->mu0, 1e-5f, 200, s->res_P,
+        ATSNE_TRY(calibrate_table(s->res_d2, s->res_d2_lo, K, r.changed, r.n_changed_dev, r0, K, s->mu0, 1e-5f, 200, s->res_P,
                                   s->res_beta, nullptr, s->res_flags, st));
     }
     // 4. the result carries the new rows' calibrated state
@@ -365,9 +374,9 @@ atsne_status commit_delete(atsne_server* s, Request& r) {
     hipStream_t st = s->s_commit;
     const int K = s->K0;
     ATSNE_HIP(hipMemsetAsync(r.n_changed_dev, 0, sizeof(int32_t), st));
-    ATSNE_TRY(serve_purge_deleted(s->res_idx, s->res_d2, s->res_P, s->res_beta, s->res_flags, K, r.nlim, s->death,
+    ATSNE_TRY(serve_purge_deleted(s->res_idx, s->res_d2, s->res_d2_lo, s->res_P, s->res_beta, s->res_flags, K, r.nlim, s->death,
                                   (int32_t)r.epoch, r.changed, r.n_changed_dev, st));
-    ATSNE_TRY(calibrate_table(s->res_d2, K, r.changed, r.n_changed_dev, r.nlim, K, s->mu0, 1e-5f, 200, s->res_P,
+    ATSNE_TRY(calibrate_table(s->res_d2, s->res_d2_lo, K, r.changed, r.n_changed_dev, r.nlim, K, s->mu0, 1e-5f, 200, s->res_P,
                               s->res_beta, nullptr, s->res_flags, st));
     ATSNE_HIP(hipMemcpyAsync(r.n_changed_host, r.n_changed_dev, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     ATSNE_HIP(hipEventRecord(r.fin, st));
@@ -622,6 +631,7 @@ extern "C" atsne_status atsne_serve_create(const atsne_serve_config* cfg, const 
         a.take<int32_t>(cap * K0);
         a.take<float>(cap * K0);
         a.take<float>(cap * K0);
+        a.take<float>(cap * K0);
         a.take<float>(cap);
         a.take<uint8_t>(cap);
         a.take<float>(cap);
@@ -631,6 +641,7 @@ extern "C" atsne_status atsne_serve_create(const atsne_serve_config* cfg, const 
         Arena b(s->res_mem, a.used);
         s->res_idx = b.take<int32_t>(cap * K0);
         s->res_d2 = b.take<float>(cap * K0);
+        s->res_d2_lo = b.take<float>(cap * K0);
         s->res_P = b.take<float>(cap * K0);
         s->res_beta = b.take<float>(cap);
         s->res_flags = b.take<uint8_t>(cap);
@@ -656,6 +667,7 @@ extern "C" atsne_status atsne_serve_create(const atsne_serve_config* cfg, const 
             if ((st = alloc_dev((void**)&b.d_desc, sizeof(int32_t) * 5 * R)) != ATSNE_OK) return fail(st);
             if ((st = alloc_dev((void**)&b.b_idx, sizeof(int32_t) * R * s->kmax)) != ATSNE_OK) return fail(st);
             if ((st = alloc_dev((void**)&b.b_d2, sizeof(float) * R * s->kmax)) != ATSNE_OK) return fail(st);
+            if ((st = alloc_dev((void**)&b.b_d2_lo, sizeof(float) * R * s->kmax)) != ATSNE_OK) return fail(st);
             if ((st = alloc_dev((void**)&b.b_flags, R)) != ATSNE_OK) return fail(st);
             if (hipHostMalloc((void**)&b.h_desc, sizeof(int32_t) * 5 * R, hipHostMallocDefault) != hipSuccess ||
                 hipStreamCreateWithFlags(&b.st, hipStreamNonBlocking) != hipSuccess ||
@@ -693,12 +705,13 @@ extern "C" atsne_status atsne_serve_create(const atsne_serve_config* cfg, const 
             bt.kc = s->kc0;
             bt.out_idx = s->res_idx + m0 * K0;
             bt.out_d2 = s->res_d2 + m0 * K0;
+            bt.out_d2_lo = s->res_d2_lo + m0 * K0;
             bt.out_flags = s->res_flags + m0;
             bt.out_stride = K0;
             st = knn_search(s->corpus, bt, p, ws, cs);
         }
         if (st == ATSNE_OK)
-            st = calibrate_table(s->res_d2, K0, nullptr, nullptr, N, K0, perplexity, 1e-5f, 200, s->res_P,
+            st = calibrate_table(s->res_d2, s->res_d2_lo, K0, nullptr, nullptr, N, K0, perplexity, 1e-5f, 200, s->res_P,
                                  s->res_beta, nullptr, s->res_flags, cs);
         hipError_t e = hipStreamSynchronize(cs);
         (void)hipFree(ws);
@@ -1044,6 +1057,7 @@ static void destroy_impl(atsne_server* s) {
         (void)hipFree(b.d_desc);
         (void)hipFree(b.b_idx);
         (void)hipFree(b.b_d2);
+        (void)hipFree(b.b_d2_lo);
         (void)hipFree(b.b_flags);
         if (b.h_desc) (void)hipHostFree(b.h_desc);
         if (b.ev) (void)hipEventDestroy(b.ev);

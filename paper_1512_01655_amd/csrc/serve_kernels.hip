@@ -29,7 +29,7 @@ __global__ __launch_bounds__(256) void serve_mark_dead(int32_t* death, const int
 // the list ends in absent entries.  Changed rows are appended to `changed`
 // and lose their calibration flags, which the re-calibration sets again.
 __global__ __launch_bounds__(256) void serve_purge(int32_t* __restrict__ res_idx, float* __restrict__ res_d2,
-                                                   float* __restrict__ res_P, float* __restrict__ res_beta,
+                                                   float* __restrict__ res_d2_lo, float* __restrict__ res_P, float* __restrict__ res_beta,
                                                    uint8_t* __restrict__ res_flags, int k, int64_t n_rows,
                                                    const int32_t* __restrict__ death, int32_t c,
                                                    int32_t* __restrict__ changed, int32_t* __restrict__ n_changed) {
@@ -40,10 +40,12 @@ __global__ __launch_bounds__(256) void serve_purge(int32_t* __restrict__ res_idx
     if (dr < c) return;  // emptied by an earlier commit
     int32_t* idx = res_idx + row * k;
     float* d2 = res_d2 + row * k;
+    float* d2l = res_d2_lo + row * k;
     if (dr == c) {
         for (int i = l; i < k; i += WAVE) {
             idx[i] = -1;
             d2[i] = INFINITY;
+            d2l[i] = 0.f;
             res_P[row * k + i] = 0.f;
         }
         if (l == 0) {
@@ -54,7 +56,7 @@ __global__ __launch_bounds__(256) void serve_purge(int32_t* __restrict__ res_idx
     }
     // the whole row is read before any entry is written
     int32_t ji[PURGE_MAXR];
-    float di[PURGE_MAXR];
+    float di[PURGE_MAXR], dli[PURGE_MAXR];
     bool keep[PURGE_MAXR];
     int removed = 0;
 #pragma unroll
@@ -62,6 +64,7 @@ __global__ __launch_bounds__(256) void serve_purge(int32_t* __restrict__ res_idx
         const int i = l + WAVE * r;
         ji[r] = i < k ? idx[i] : -1;
         di[r] = i < k ? d2[i] : INFINITY;
+        dli[r] = i < k ? d2l[i] : 0.f;
         keep[r] = ji[r] >= 0 && death[ji[r]] > c;
         removed += __popcll(ballot(ji[r] >= 0 && !keep[r]));
     }
@@ -74,12 +77,14 @@ __global__ __launch_bounds__(256) void serve_purge(int32_t* __restrict__ res_idx
             const int p = base + __popcll(m & lanemask_lt());
             idx[p] = ji[r];
             d2[p] = di[r];
+            d2l[p] = dli[r];
         }
         base += __popcll(m);
     }
     for (int i = base + l; i < k; i += WAVE) {
         idx[i] = -1;
         d2[i] = INFINITY;
+        d2l[i] = 0.f;
     }
     if (l == 0) {
         res_flags[row] &= (uint8_t)~(ATSNE_FLAG_DEGENERATE | ATSNE_FLAG_NOT_CONVERGED);
@@ -128,14 +133,14 @@ atsne_status serve_mark_deleted(int32_t* death, const int32_t* ids, int64_t M, i
     return ATSNE_OK;
 }
 
-atsne_status serve_purge_deleted(int32_t* res_idx, float* res_d2, float* res_P, float* res_beta, uint8_t* res_flags,
-                                 int k, int64_t n_rows, const int32_t* death, int32_t c, int32_t* changed,
-                                 int32_t* n_changed, hipStream_t st) {
+atsne_status serve_purge_deleted(int32_t* res_idx, float* res_d2, float* res_d2_lo, float* res_P, float* res_beta,
+                                 uint8_t* res_flags, int k, int64_t n_rows, const int32_t* death, int32_t c,
+                                 int32_t* changed, int32_t* n_changed, hipStream_t st) {
     ATSNE_REQUIRE(k >= 1 && k <= WAVE * PURGE_MAXR, ATSNE_E_K_RANGE, "resident k=%d above %d", k, WAVE * PURGE_MAXR);
     if (n_rows == 0) return ATSNE_OK;
     ProfScope ps_("serve_purge", st);
-    serve_purge<<<blocks_of(n_rows, 4), 256, 0, st>>>(res_idx, res_d2, res_P, res_beta, res_flags, k, n_rows, death,
-                                                      c, changed, n_changed);
+    serve_purge<<<blocks_of(n_rows, 4), 256, 0, st>>>(res_idx, res_d2, res_d2_lo, res_P, res_beta, res_flags, k,
+                                                      n_rows, death, c, changed, n_changed);
     ATSNE_LAUNCH_CHECK();
     return ATSNE_OK;
 }

@@ -72,6 +72,15 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
     return v;
 }
 
+// Error-free sum (Knuth's TwoSum): returns s = fl(a + b) and sets e so that
+// s + e = a + b exactly.  Symmetric in a and b.
+__device__ __forceinline__ float two_sum(float a, float b, float& e) {
+    const float s = a + b;
+    const float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+    return s;
+}
+
 // Total order on floats as unsigned integers (negatives included).
 __device__ __forceinline__ uint32_t f2ord(float f) {
     uint32_t u = __float_as_uint(f);

@@ -42,8 +42,9 @@ def test_host_side_validation():
     assert L.atsne_knn_workspace_size(1, 1, 4, 0, 1, 0, ctypes.byref(b)) == atsne.E_INVALID_ARG
     assert L.atsne_knn_workspace_size(70000, 70000, 784, 0, 90, 0, ctypes.byref(b)) == atsne.OK
     assert b.value > 70000 * 784 * 4
-    assert L.atsne_knn(None, 10, 4, 4, 0, 3, 0, None, None, None, None, 0, None) == atsne.E_INVALID_ARG
-    assert L.atsne_calibrate_p(None, 10, 30, 10.0, 0.0, 0, 0, None, None, None, None, None) == atsne.E_INVALID_ARG
+    assert L.atsne_knn(None, 10, 4, 4, 0, 3, 0, None, None, None, None, None, 0, None) == atsne.E_INVALID_ARG
+    assert L.atsne_calibrate_p(None, None, 10, 30, 10.0, 0.0, 0, 0, None, None, None, None, None) == \
+        atsne.E_INVALID_ARG
     assert L.atsne_symmetrize_workspace_size(100, 900, ctypes.byref(b)) == atsne.OK
     assert L.atsne_serve_create(None, None, 0, 0, 30.0, None) == atsne.E_INVALID_ARG
     assert b"bad arguments" in L.atsne_last_error()

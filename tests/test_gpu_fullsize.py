@@ -145,13 +145,14 @@ def test_config4_fp8_sample_10k(A):
     X = datagen.mixture_anisotropic()
     N, k, kc, mu = X.shape[0], 150, 300, 50.0
     say("  GPU knn fp8 N=%d D=%d k=%d kc=%d" % (N, X.shape[1], k, kc))
-    idx, d2, fl = A.knn(torch.from_numpy(X).cuda(), k, prec="fp8", k_cand=kc)
+    lo = torch.empty((N, k), dtype=torch.float32, device="cuda")
+    idx, d2, fl = A.knn(torch.from_numpy(X).cuda(), k, prec="fp8", k_cand=kc, d2_lo=lo)
     rows = np.sort(np.random.default_rng(9).choice(N, size=10000, replace=False)).astype(np.int32)
     qi = torch.from_numpy(rows.astype(np.int64)).cuda()
     g_idx, g_d2 = idx[qi].cpu().numpy(), d2[qi].cpu().numpy()
-    P, beta, perp, _ = A.calibrate_p(d2[qi].contiguous(), mu)
+    P, beta, perp, _ = A.calibrate_p(d2[qi].contiguous(), mu, d2_lo=lo[qi].contiguous())
     g_P = P.cpu().numpy().astype(np.float64)
-    del idx, d2, fl
+    del idx, d2, fl, lo
     torch.cuda.empty_cache()
     td = parity.check_rows_valid(X, rows, g_idx, g_d2)
     o_idx, o_d2, o_nx = _oracle_knn_chunked(X, k, rows, 1000)

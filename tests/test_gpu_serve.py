@@ -28,8 +28,9 @@ def _standalone(A, X, ids, mu):
     k = int(math.floor(3 * mu))
     Xt = torch.from_numpy(X).cuda()
     q = torch.from_numpy(np.asarray(ids, np.int32)).cuda()
-    idx, d2, fl = A.knn(Xt, k, query_ids=q)
-    P, beta, perp, fl = A.calibrate_p(d2, mu, flags=fl)
+    lo = torch.empty((len(ids), k), dtype=torch.float32, device="cuda")
+    idx, d2, fl = A.knn(Xt, k, query_ids=q, d2_lo=lo)
+    P, beta, perp, fl = A.calibrate_p(d2, mu, flags=fl, d2_lo=lo)
     torch.cuda.synchronize()
     return dict(idx=idx.cpu().numpy(), d2=d2.cpu().numpy(), P=P.cpu().numpy(), beta=beta.cpu().numpy())
 
@@ -445,9 +446,20 @@ def test_serve_failed_launch_fails_every_request(A, monkeypatch):
     s = A.Server(torch.from_numpy(X).cuda(), 30.0, max_batch_rows=300, capacity_rows=4000)
     monkeypatch.delenv("ATSNE_SERVE_FAIL_LAUNCH")
     rng = np.random.default_rng(6)
-    rids = [s.refine(rng.choice(3000, size=1000, replace=False).astype(np.int32), 30.0) for _ in range(3)]
-    rids.append(s.insert(torch.from_numpy(_corpus(n=200, seed=39)).cuda()))
-    rids.append(s.refine(rng.choice(3000, size=50, replace=False).astype(np.int32), 10.0))
+    # the failure can come before every submission is in: from then on a
+    # submission is refused with the failure's status
+    subs = [lambda: s.refine(rng.choice(3000, size=1000, replace=False).astype(np.int32), 30.0)] * 3
+    subs += [lambda: s.insert(torch.from_numpy(_corpus(n=200, seed=39)).cuda()),
+             lambda: s.refine(rng.choice(3000, size=50, replace=False).astype(np.int32), 10.0)]
+    rids, refused = [], 0
+    for sub in subs:
+        try:
+            rids.append(sub())
+        except A.AtsneError as e:
+            assert e.status == A.E_NOMEM
+            refused += 1
+    say("    accepted %d, refused %d" % (len(rids), refused))
+    assert rids, "the first submission comes before any launch"
     deadline = time.time() + 60
     res = {}
     while len(res) < len(rids) and time.time() < deadline:
