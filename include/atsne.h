@@ -181,6 +181,18 @@ atsne_status atsne_symmetrize(const int32_t* nbr_idx, const float* P_cond, int64
                               int64_t* row_ptr, int32_t* col, float* val, int64_t* nnz_host, void* ws,
                               size_t ws_bytes, void* stream);
 
+/* As atsne_symmetrize, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): no workspace argument, and the call allocates nothing.  Its
+ * scratch is a 64 MiB device array inside the library, one per GPU, held
+ * until the process ends; that limits it to about 1.4 million conditional
+ * entries (N * k), and larger inputs return ATSNE_E_NOMEM before any work.
+ * Calls that overlap on one GPU share that array and race: serialise them.
+ * Same outputs, bit for bit, as atsne_symmetrize; synchronises the stream
+ * once (to read nnz). */
+atsne_status atsne_symmetrize_noalloc(const int32_t* nbr_idx, const float* P_cond, int64_t N, int32_t k,
+                                      int64_t* row_ptr, int32_t* col, float* val, int64_t* nnz_host, void* stream);
+
 /* As atsne_symmetrize for conditional rows of varying length given as CSR:
  * in_ptr [N+1] int64 with in_ptr[0] = 0, in_col/in_val [in_ptr[N]] (device),
  * columns distinct within a row, in [0, N), no self.  Output capacity

@@ -25,7 +25,7 @@ EXPORTS = [
     "atsne_last_error", "atsne_version", "atsne_device_info", "atsne_profile_enable", "atsne_profile_read",
     "atsne_knn_workspace_size", "atsne_knn", "atsne_knn_subset",
     "atsne_calibrate_p",
-    "atsne_symmetrize_workspace_size", "atsne_symmetrize", "atsne_symmetrize_csr",
+    "atsne_symmetrize_workspace_size", "atsne_symmetrize", "atsne_symmetrize_csr", "atsne_symmetrize_noalloc",
     "atsne_ivf_build", "atsne_ivf_partition", "atsne_ivf_knn", "atsne_ivf_fit", "atsne_ivf_destroy",
     "atsne_attractive_forces", "atsne_order_workspace_size", "atsne_order_density", "atsne_order_neighbourhood",
     "atsne_serve_create", "atsne_serve_submit_insert", "atsne_serve_submit_refine", "atsne_serve_submit_delete",
@@ -91,6 +91,7 @@ def load(path: Path | None = None) -> ctypes.CDLL:
         "atsne_calibrate_p": [_p, _p, _i64, _i32, _f32, _f32, _i32, _i32, _p, _p, _p, _p, _p],
         "atsne_symmetrize_workspace_size": [_i64, _i64, _p],
         "atsne_symmetrize": [_p, _p, _i64, _i32, _p, _p, _p, _p, _p, _sz, _p],
+        "atsne_symmetrize_noalloc": [_p, _p, _i64, _i32, _p, _p, _p, _p, _p],
         "atsne_symmetrize_csr": [_p, _p, _p, _i64, _i64, _p, _p, _p, _p, _p, _sz, _p],
         "atsne_attractive_forces": [_p, _p, _p, _i64, _i64, _p, _i32, _p, _f32, _f32, _i32, _f32, _p, _p],
         "atsne_ivf_build": [_p, _i64, _i32, _i32, _p, _i32, _p, _p],
@@ -223,6 +224,24 @@ def symmetrize(nbr_idx: torch.Tensor, P_cond: torch.Tensor, stream=None, workspa
     _check(L.atsne_symmetrize(_ptr(nbr_idx), _ptr(P_cond), N, k, _ptr(row_ptr), _ptr(col), _ptr(val),
                               ctypes.byref(nnz), _ptr(workspace), workspace.numel(), _stream(stream)))
     return row_ptr, col[:nnz.value], val[:nnz.value]
+
+
+def symmetrize_noalloc(nbr_idx: torch.Tensor, P_cond: torch.Tensor, row_ptr: torch.Tensor, col: torch.Tensor,
+                       val: torch.Tensor, stream=None) -> int:
+    """atsne_symmetrize_noalloc into caller-allocated outputs (row_ptr [N+1] int64, col/val with capacity 2*N*k);
+    returns nnz.  The call itself allocates nothing."""
+    L = load()
+    _dev(nbr_idx, torch.int32, "nbr_idx")
+    _dev(P_cond, torch.float32, "P_cond")
+    N, k = nbr_idx.shape
+    if not (nbr_idx.is_contiguous() and P_cond.is_contiguous() and P_cond.shape == nbr_idx.shape):
+        raise ValueError("contiguous nbr_idx and P_cond of one shape are required")
+    if row_ptr.numel() < N + 1 or col.numel() < 2 * N * k or val.numel() < 2 * N * k:
+        raise ValueError("output capacity too small")
+    nnz = ctypes.c_int64()
+    _check(L.atsne_symmetrize_noalloc(_ptr(nbr_idx), _ptr(P_cond), N, k, _ptr(row_ptr), _ptr(col), _ptr(val),
+                                      ctypes.byref(nnz), _stream(stream)))
+    return nnz.value
 
 
 def symmetrize_csr(in_ptr: torch.Tensor, in_col: torch.Tensor, in_val: torch.Tensor, stream=None):

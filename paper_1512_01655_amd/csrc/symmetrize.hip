@@ -21,6 +21,7 @@
 // All keys are distinct and each output value is the sum of at most two
 // addends, so the result is bit-for-bit deterministic.
 #include <algorithm>
+#include <mutex>
 
 #include <rocprim/device/device_radix_sort.hpp>
 
@@ -263,7 +264,55 @@ static atsne_status sym_run(const SymPlan& p, RowsIn rin, const int32_t* in_col,
     return ATSNE_OK;
 }
 
+// Allocation-free variant: the scratch lives in this file-scope device
+// array, one copy per GPU the library runs on, held until the process ends.
+// Host code never uses the array's name as a device address: each device's
+// copy is looked up once with hipGetSymbolAddress (with that device current)
+// and that address is what the kernels receive.  Calls on one GPU share its
+// copy, so calls that overlap on one GPU race; every kernel overwrites what
+// it reads, so the previous call's contents need no clearing.
+constexpr size_t SYM_NOALLOC_SCRATCH = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[SYM_NOALLOC_SCRATCH];
+
+static atsne_status noalloc_scratch(void** out) {
+    constexpr int MAX_DEV = 64;
+    static std::mutex mu;
+    static void* addr[MAX_DEV] = {};
+    int dev = -1;
+    ATSNE_HIP(hipGetDevice(&dev));
+    ATSNE_REQUIRE(dev >= 0 && dev < MAX_DEV, ATSNE_E_UNSUPPORTED, "device ordinal %d above %d", dev, MAX_DEV - 1);
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        ATSNE_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        ATSNE_REQUIRE(p != nullptr, ATSNE_E_HIP, "no device address for the symmetrisation scratch");
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return ATSNE_OK;
+}
+
 }  // namespace atsne
+
+extern "C" atsne_status atsne_symmetrize_noalloc(const int32_t* nbr_idx, const float* P_cond, int64_t N, int32_t k,
+                                                 int64_t* row_ptr, int32_t* col, float* val, int64_t* nnz_host,
+                                                 void* stream) {
+    using namespace atsne;
+    clear_error();
+    ATSNE_REQUIRE(nbr_idx && P_cond && row_ptr && col && val && nnz_host, ATSNE_E_INVALID_ARG, "null pointer");
+    ATSNE_REQUIRE(N >= 1 && N < (1ll << 31), ATSNE_E_INVALID_ARG, "N=%lld out of range", (long long)N);
+    ATSNE_REQUIRE(k >= 1 && k <= N - 1, ATSNE_E_K_RANGE, "k=%d out of [1, N-1]", k);
+    SymPlan p;
+    sym_plan(N, N * (int64_t)k, p);
+    ATSNE_REQUIRE(p.total <= SYM_NOALLOC_SCRATCH, ATSNE_E_NOMEM,
+                  "N=%lld, k=%d needs %zu bytes of scratch, above the %zu of the allocation-free symmetrisation "
+                  "(use atsne_symmetrize)",
+                  (long long)N, k, p.total, SYM_NOALLOC_SCRATCH);
+    void* ws = nullptr;
+    ATSNE_TRY(noalloc_scratch(&ws));
+    RowsIn rin{nullptr, k};
+    return sym_run(p, rin, nbr_idx, P_cond, row_ptr, col, val, nnz_host, ws, static_cast<hipStream_t>(stream));
+}
 
 extern "C" atsne_status atsne_symmetrize_workspace_size(int64_t N, int64_t nnz_in, size_t* bytes) {
     atsne::clear_error();
