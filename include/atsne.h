@@ -185,7 +185,7 @@ atsne_status atsne_symmetrize(const int32_t* nbr_idx, const float* P_cond, int64
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
  * allocation): no workspace argument, and the call allocates nothing.  Its
  * scratch is a 64 MiB device array inside the library, one per GPU, held
- * until the process ends; that limits it to about 1.4 million conditional
+ * until the process ends; that limits it to about 1.8 million conditional
  * entries (N * k), and larger inputs return ATSNE_E_NOMEM before any work.
  * Calls that overlap on one GPU share that array and race: serialise them.
  * Same outputs, bit for bit, as atsne_symmetrize; synchronises the stream

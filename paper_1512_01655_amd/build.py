@@ -20,7 +20,7 @@ LIB = PKG / "libatsne.so"
 BUILD = PKG / "_build"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["runtime.cpp", "knn.hip", "calibrate.hip", "symmetrize.hip", "forces.hip", "order.hip", "ivf.hip", "serve_kernels.hip", "serve.cpp"]
+SOURCES = ["runtime.cpp", "radix.hip", "knn.hip", "calibrate.hip", "symmetrize.hip", "forces.hip", "order.hip", "ivf.hip", "serve_kernels.hip", "serve.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall", "-Wno-unused-function",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

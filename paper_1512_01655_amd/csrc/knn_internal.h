@@ -109,9 +109,15 @@ atsne_status calibrate_table(const float* d2, const float* d2_lo, int64_t stride
                              const int32_t* n_rows_dev, int64_t n_rows, int k, float mu, float tol, int max_iter,
                              float* P, float* beta, float* perp, uint8_t* flags, hipStream_t st);
 
-// Ascending 64-bit key sort (radix); tmp holds sort_u64_temp_bytes(n) bytes.
+// Ascending 64-bit key sort (hand-written LSD radix over bits [begin_bit,
+// end_bit), keys equal elsewhere; stable), optionally carrying a 32-bit value
+// per key; tmp holds sort_u64_temp_bytes(n) bytes; in and out must not
+// overlap.
 size_t sort_u64_temp_bytes(int64_t n);
-atsne_status sort_u64(void* tmp, size_t tmp_bytes, const uint64_t* in, uint64_t* out, int64_t n, hipStream_t st);
+atsne_status sort_u64(void* tmp, size_t tmp_bytes, const uint64_t* in, uint64_t* out, int64_t n, hipStream_t st,
+                      int begin_bit = 0, int end_bit = 64);
+atsne_status sort_pairs_u64(void* tmp, size_t tmp_bytes, const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
+                            uint32_t* vout, int64_t n, hipStream_t st, int begin_bit = 0, int end_bit = 64);
 
 // Plan a search restricted to per-block tile lists (Batch::blk_q set):
 // M rows in n_blocks blocks, S splits per block.

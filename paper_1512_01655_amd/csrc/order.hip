@@ -18,7 +18,6 @@
 // with a 64-bit radix sort.
 #include <climits>
 
-#include <rocprim/device/device_radix_sort.hpp>
 
 #include "knn_internal.h"
 #include "wave.h"
@@ -105,18 +104,6 @@ __global__ __launch_bounds__(256) void ord_collect(const uint32_t* __restrict__ 
 static unsigned blocks(int64_t n) { return (unsigned)std::max<int64_t>(1, ceil_div(n, 256)); }
 
 static size_t sort_temp_bytes(int64_t n) { return sort_u64_temp_bytes(n); }
-
-size_t sort_u64_temp_bytes(int64_t n) {
-    size_t bytes = 0;
-    (void)rocprim::radix_sort_keys(nullptr, bytes, (const uint64_t*)nullptr, (uint64_t*)nullptr, (size_t)n, 0, 64);
-    return std::max<size_t>(bytes, 1);
-}
-
-atsne_status sort_u64(void* tmp, size_t tmp_bytes, const uint64_t* in, uint64_t* out, int64_t n, hipStream_t st) {
-    if (n == 0) return ATSNE_OK;
-    ATSNE_HIP(rocprim::radix_sort_keys(tmp, tmp_bytes, in, out, (size_t)n, 0, 64, st));
-    return ATSNE_OK;
-}
 
 struct OrderWs {
     uint64_t *keys_in, *keys_out;

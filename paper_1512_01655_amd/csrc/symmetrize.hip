@@ -4,40 +4,38 @@
 // only the per-point conditional rows are stored upstream).  The output is
 // CSR with ascending columns over the union of the neighbour patterns.
 //
-// Device pipeline (HBM bound; one global key sort instead of per-row sorts,
-// so hub rows of the kNN graph cost no more than any other entries):
-//   sym_keys     each conditional entry (i, j, p_{j|i}) becomes two keys,
-//                (row i, column j, own) and (row j, column i, mirrored),
-//                both carrying p_{j|i}
-//   radix sort   of the 2*nnz (key, value) pairs over the 2b+1 key bits
-//                (b bits per index), giving row-major, column-ascending order
-//                with the own half of a column before its mirrored half
-//   sym_heads    per 1024 sorted entries: number of distinct (row, column)
-//   scan         exclusive block offsets (one workgroup)
-//   sym_emit     each distinct (row, column) adds its at most two addends,
-//                scales by 1/(2N) and lands at its CSR position; the first
-//                entry of each row (and every empty row before it) writes
-//                row_ptr
-// All keys are distinct and each output value is the sum of at most two
-// addends, so the result is bit-for-bit deterministic.
+// A row's union joins its own entries (its conditional row) with its
+// mirrored entries (the rows that list it), so the pattern's transpose is
+// built first, without global atomics (on a multi-die GPU they serialise):
+//   sym_pack       every entry (i, j, p) as the key (j << 32 | i) with value p
+//                  (an ignored entry gets the key N << 32, after every column)
+//   radix sort     stable, by the column bits only: the input is row-major,
+//                  so each column's run comes out ascending by its source row
+//                  i, i.e. row j's mirrored entries sorted by their column
+//   sym_runs       the start of every column's run
+//   sym_row_count  per row, own + mirrored - columns in both (a binary search
+//                  of each own column in the row's run), then a multi-block
+//                  scan gives the row pointers
+//   sym_row_emit   per row: its own entries ranked by column in LDS; every
+//                  entry goes to (own entries before it) + (mirrored entries
+//                  before it) - (columns in both before it), a column in both
+//                  carrying p_own + p_mirrored (in that order), scaled 1/(2N)
+// Every position and sum is fixed by the input, so the result is bit-for-bit
+// deterministic.  Entries whose column is outside [0, N) or equal to their
+// row are ignored; columns within a conditional row must be distinct, and a
+// row holds at most 1024 own entries.
 #include <algorithm>
+#include <climits>
 #include <mutex>
 
-#include <rocprim/device/device_radix_sort.hpp>
-
-#include "common.h"
+#include "knn_internal.h"
 #include "wave.h"
 
 namespace atsne {
 
-constexpr int SYM_BLOCK = 1024;  // sorted entries per sym_heads / sym_emit workgroup (256 threads x 4)
-constexpr uint64_t SYM_NONE = ~0ull;  // sentinel key: (SYM_NONE >> 1) equals no real (row, column) pair
-// Radix passes at every size above one block's worth: rocPRIM's default
-// switches to a merge sort below 2^20 items, which is slower here (18 merge
-// launches for the 3.6e5 pairs of N = 2000, k = 90: the whole
-// symmetrisation took 0.27 ms that way, 0.125 ms with radix passes).
-using SymSortConfig = rocprim::radix_sort_config<rocprim::default_config, rocprim::default_config,
-                                                 rocprim::default_config, 0>;
+constexpr int SYM_OWN_MAX = 1024;  // own entries of a row ranked in LDS
+constexpr int SYM_RUN_LDS = 1024;  // mirrored run cached in LDS (longer runs are searched in place)
+constexpr int SYM_SCAN_BLOCK = 4096;  // counts per workgroup of the row-pointer scan
 
 // Row extent of the conditional input: CSR (in_ptr) or fixed k.
 struct RowsIn {
@@ -47,61 +45,131 @@ struct RowsIn {
     __device__ __forceinline__ int64_t end(int64_t i) const { return ptr ? ptr[i + 1] : (i + 1) * k; }
 };
 
-// Key layout: row << s | column << 1 | origin (0 own, 1 mirrored), s = b + 1.
-__global__ __launch_bounds__(256) void sym_keys(RowsIn rin, const int32_t* __restrict__ col,
-                                                const float* __restrict__ val, int64_t N, int s,
-                                                ulonglong2* __restrict__ key, float2* __restrict__ kval) {
+__device__ __forceinline__ bool sym_valid(int32_t j, int64_t i, int64_t N) { return j >= 0 && j < N && j != i; }
+
+__global__ __launch_bounds__(64) void sym_zero(int32_t* __restrict__ a, int n) {
+    if ((int)threadIdx.x < n) a[threadIdx.x] = 0;
+}
+
+// One wave per input row: the transposed keys of its entries.
+__global__ __launch_bounds__(256) void sym_pack(RowsIn rin, const int32_t* __restrict__ col,
+                                                const float* __restrict__ val, int64_t N,
+                                                uint64_t* __restrict__ key, uint32_t* __restrict__ pv) {
     const int l = lane_id();
     const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= N) return;
     const int64_t b = rin.begin(i), e = rin.end(i);
-    const uint64_t ui = (uint64_t)i;
     for (int64_t t = b + l; t < e; t += WAVE) {
-        const uint64_t j = (uint64_t)(uint32_t)col[t];
-        const float p = val[t];
-        key[t] = make_ulonglong2((ui << s) | (j << 1), (j << s) | (ui << 1) | 1);
-        kval[t] = make_float2(p, p);
+        const int32_t j = col[t];
+        const bool ok = sym_valid(j, i, N);
+        key[t] = ((uint64_t)(ok ? (uint32_t)j : (uint32_t)N) << 32) | (uint32_t)i;
+        pv[t] = __float_as_uint(val[t]);
     }
 }
 
-// Sum of v over a 256-thread workgroup (result valid in every thread).
-__device__ __forceinline__ int block_sum256(int v, int* red) {
+// run[j] = first sorted position of column j (run[N] = number of kept
+// entries): each position writes the starts of the columns in (previous
+// column, its column].
+__global__ __launch_bounds__(256) void sym_runs(const uint64_t* __restrict__ key, int64_t E, int64_t N,
+                                                int64_t* __restrict__ run) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e > E) return;
+    const int64_t jp = e > 0 ? (int64_t)(key[e - 1] >> 32) : -1;
+    const int64_t j = e < E ? (int64_t)(key[e] >> 32) : N;
+    for (int64_t r = jp + 1; r <= std::min(j, N); ++r) run[r] = e;
+}
+
+// First position in [0, n) of sorted src rows (low words of keys) >= c.
+__device__ __forceinline__ int lower_src(const uint64_t* k, int n, int32_t c) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((int32_t)(uint32_t)k[mid] < c)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+__device__ __forceinline__ int lower_lds(const int32_t* a, int n, int32_t c) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] < c)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// One wave per row: distinct columns of the union.
+__global__ __launch_bounds__(256) void sym_row_count(RowsIn rin, const int32_t* __restrict__ col, int64_t N,
+                                                     const uint64_t* __restrict__ key, const int64_t* __restrict__ run,
+                                                     int64_t* __restrict__ cnt, int32_t* __restrict__ err) {
+    __shared__ int32_t cache_all[4][SYM_RUN_LDS];
+    const int l = lane_id();
     const int w = threadIdx.x >> 6;
-    v = wave_sum(v);
-    if (lane_id() == 0) red[w] = v;
-    __syncthreads();
-    return red[0] + red[1] + red[2] + red[3];
-}
-
-__global__ __launch_bounds__(256) void sym_heads(const uint64_t* __restrict__ key, int64_t n,
-                                                 int64_t* __restrict__ block_sums) {
-    __shared__ int red[4];
-    const int64_t base = (int64_t)blockIdx.x * SYM_BLOCK + 4 * threadIdx.x;
-    int c = 0;
-    if (base < n) {
-        uint64_t prev = base > 0 ? key[base - 1] >> 1 : SYM_NONE;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            if (base + q < n) {
-                const uint64_t kq = key[base + q] >> 1;
-                c += kq != prev;
-                prev = kq;
-            }
-        }
+    const int64_t i = (int64_t)blockIdx.x * 4 + w;
+    if (i >= N) return;  // waves are independent: no workgroup barrier below
+    const int64_t b = rin.begin(i), e = rin.end(i);
+    if (e - b > SYM_OWN_MAX) {
+        if (l == 0) atomicOr(err, 1);
+        if (l == 0) cnt[i] = 0;
+        return;
     }
-    const int tot = block_sum256(c, red);
-    if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
+    const int64_t m0 = run[i];
+    const int n_in = (int)(run[i + 1] - m0);
+    const uint64_t* mk = key + m0;
+    int32_t* cache = cache_all[w];
+    const bool in_lds = n_in <= SYM_RUN_LDS;
+    if (in_lds)
+        for (int x = l; x < n_in; x += WAVE) cache[x] = (int32_t)(uint32_t)mk[x];
+    wave_sync();
+    int n_own = 0, both = 0;
+    for (int64_t t = b + l; t < e; t += WAVE) {
+        const int32_t c = col[t];
+        const bool ok = sym_valid(c, i, N);
+        bool hit = false;
+        if (ok) {
+            const int lb = in_lds ? lower_lds(cache, n_in, c) : lower_src(mk, n_in, c);
+            hit = lb < n_in && (in_lds ? cache[lb] : (int32_t)(uint32_t)mk[lb]) == c;
+        }
+        n_own += __popcll(ballot(ok));
+        both += __popcll(ballot(hit));
+    }
+    if (l == 0) cnt[i] = (int64_t)n_own + n_in - both;
 }
 
-// In-place exclusive scan of nb block counts by one workgroup (each thread
-// takes a contiguous run); *total receives the sum.
-__global__ __launch_bounds__(1024) void sym_scan_blocks(int64_t* __restrict__ bs, int64_t nb, int64_t* __restrict__ total) {
+// Multi-block exclusive scan of n int64 counts into out[0..n] (out[n] the
+// total): block sums, a one-workgroup scan of those, then each block's scan.
+__global__ __launch_bounds__(1024) void sym_block_sums(const int64_t* __restrict__ c, int64_t n,
+                                                       int64_t* __restrict__ bs) {
     __shared__ int64_t wsum[16];
     const int t = threadIdx.x, l = t & 63, w = t >> 6;
-    const int64_t per = (nb + 1023) / 1024;
-    const int64_t b0 = std::min<int64_t>(nb, t * per), b1 = std::min<int64_t>(nb, b0 + per);
+    const int64_t base = (int64_t)blockIdx.x * SYM_SCAN_BLOCK + 4 * t;
     int64_t s = 0;
-    for (int64_t b = b0; b < b1; ++b) s += bs[b];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s += base + q < n ? c[base + q] : 0;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (l == 0) wsum[w] = s;
+    __syncthreads();
+    if (t == 0) {
+        int64_t tot = 0;
+        for (int i = 0; i < 16; ++i) tot += wsum[i];
+        bs[blockIdx.x] = tot;
+    }
+}
+
+__global__ __launch_bounds__(1024) void sym_scan_small(const int64_t* __restrict__ in, int64_t n,
+                                                       int64_t* __restrict__ out) {
+    __shared__ int64_t wsum[16];
+    const int t = threadIdx.x, l = t & 63, w = t >> 6;
+    const int64_t per = (n + 1023) / 1024;
+    const int64_t b0 = std::min<int64_t>(n, t * per), b1 = std::min<int64_t>(n, b0 + per);
+    int64_t s = 0;
+    for (int64_t i = b0; i < b1; ++i) s += in[i];
     int64_t incl = s;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -110,49 +178,28 @@ __global__ __launch_bounds__(1024) void sym_scan_blocks(int64_t* __restrict__ bs
     }
     if (l == 63) wsum[w] = incl;
     __syncthreads();
-    int64_t woff = 0;
-    for (int i = 0; i < w; ++i) woff += wsum[i];
-    int64_t run = woff + incl - s;
-    for (int64_t b = b0; b < b1; ++b) {
-        const int64_t v = bs[b];
-        bs[b] = run;
+    int64_t run = incl - s;
+    for (int i = 0; i < w; ++i) run += wsum[i];
+    for (int64_t i = b0; i < b1; ++i) {
+        const int64_t v = in[i];
+        out[i] = run;
         run += v;
     }
-    if (t == 1023) *total = woff + incl;
+    if (t == 1023) out[n] = run;
 }
 
-struct EmitArgs {
-    const uint64_t* key;
-    const float* v;
-    int64_t n, N;
-    int s;
-    uint64_t cmask;  // (1 << b) - 1
-    const int64_t* block_off;
-    float inv_norm;
-    int64_t* row_ptr;
-    int32_t* col;
-    float* val;
-};
-
-__global__ __launch_bounds__(256) void sym_emit(EmitArgs a) {
-    __shared__ int64_t wsum[4];
+__global__ __launch_bounds__(1024) void sym_block_scan(const int64_t* __restrict__ c, int64_t n,
+                                                       const int64_t* __restrict__ boff, int64_t* __restrict__ out) {
+    __shared__ int64_t wsum[16];
     const int t = threadIdx.x, l = t & 63, w = t >> 6;
-    const int64_t base = (int64_t)blockIdx.x * SYM_BLOCK + 4 * t;
-    // kk[0] = predecessor, kk[1..4] = own entries, kk[5] = successor
-    uint64_t kk[6];
-    int c = 0;
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-        const int64_t e = base + q - 1;
-        kk[q] = (base < a.n && e >= 0 && e < a.n) ? a.key[e] : SYM_NONE;
-    }
-    bool h[4];
+    const int64_t base = (int64_t)blockIdx.x * SYM_SCAN_BLOCK + 4 * t;
+    int64_t v[4], s = 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        h[q] = base + q < a.n && (kk[q + 1] >> 1) != (kk[q] >> 1);
-        c += h[q];
+        v[q] = base + q < n ? c[base + q] : 0;
+        s += v[q];
     }
-    int64_t incl = c;
+    int64_t incl = s;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
         const int64_t tv = __shfl_up(incl, o, 64);
@@ -160,107 +207,203 @@ __global__ __launch_bounds__(256) void sym_emit(EmitArgs a) {
     }
     if (l == 63) wsum[w] = incl;
     __syncthreads();
-    if (base >= a.n) return;
-    int64_t woff = 0;
-    for (int i = 0; i < w; ++i) woff += wsum[i];
-    int64_t pos = a.block_off[blockIdx.x] + woff + incl - c;
-    int64_t prow = base > 0 ? (int64_t)(kk[0] >> a.s) : -1;
+    int64_t run = boff[blockIdx.x] + incl - s;
+    for (int i = 0; i < w; ++i) run += wsum[i];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const int64_t e = base + q;
-        if (e < a.n) {
-            const uint64_t kq = kk[q + 1];
-            const int64_t row = (int64_t)(kq >> a.s);
-            // rows (prow, row] start here: row's first entry and the empty rows before it
-            for (int64_t r = prow + 1; r <= std::min(row, a.N - 1); ++r) a.row_ptr[r] = pos;
-            prow = row;
-            if (h[q]) {
-                float x = a.v[e];
-                if ((kk[q + 2] >> 1) == (kq >> 1)) x += a.v[e + 1];  // own + mirrored
-                a.col[pos] = (int32_t)((kq >> 1) & a.cmask);
-                a.val[pos] = x * a.inv_norm;
-                ++pos;
+        if (base + q < n) out[base + q] = run;
+        run += v[q];
+    }
+    if (base < n && base + 4 >= n) out[n] = run;  // the thread holding the last count writes the total
+}
+
+// One wave per row, four rows per workgroup; a row holds at most CAP own
+// entries (its LDS) and its mirrored run is cached in LDS up to RUN entries.
+template <int CAP, int RUN>
+__global__ __launch_bounds__(256) void sym_row_emit(RowsIn rin, const int32_t* __restrict__ col,
+                                                    const float* __restrict__ val, int64_t N,
+                                                    const uint64_t* __restrict__ key, const uint32_t* __restrict__ pv,
+                                                    const int64_t* __restrict__ run,
+                                                    const int64_t* __restrict__ row_ptr, float inv_norm, int64_t cap,
+                                                    int32_t* __restrict__ out_col, float* __restrict__ out_val) {
+    struct alignas(16) RowLds {
+        int32_t ocol[CAP];      // own columns (input order, kept entries)
+        float oval[CAP];        // their values, then own + mirrored for columns in both
+        int32_t olb[CAP];       // mirrored entries before each own column
+        int32_t orank[CAP];     // rank of each own column among the own columns
+        int32_t scol[CAP];      // own columns in ascending order
+        int32_t mpref[CAP + 1]; // flags of columns in both by rank, then their exclusive prefix
+        int32_t cache[RUN];     // the mirrored run's columns
+    };
+    __shared__ RowLds lds_all[4];
+    const int l = lane_id();
+    const int w = threadIdx.x >> 6;
+    RowLds& L = lds_all[w];
+    const int64_t i = (int64_t)blockIdx.x * 4 + w;
+    if (i >= N) return;  // waves are independent: no workgroup barrier below
+    const int64_t b = rin.begin(i), e = rin.end(i);
+    if (e - b > CAP) return;  // refused by the count (error flag)
+    const int64_t m0 = run[i];
+    const int n_in = (int)(run[i + 1] - m0);
+    const uint64_t* mk = key + m0;
+    const bool in_lds = n_in <= RUN;
+    if (in_lds)
+        for (int x = l; x < n_in; x += WAVE) L.cache[x] = (int32_t)(uint32_t)mk[x];
+    // kept own entries, compacted in input order
+    int n_own = 0;
+    for (int64_t t0 = b; t0 < e; t0 += WAVE) {
+        const int64_t t = t0 + l;
+        const int32_t c = t < e ? col[t] : -1;
+        const bool ok = t < e && sym_valid(c, i, N);
+        const uint64_t m = ballot(ok);
+        if (ok) {
+            const int p = n_own + __popcll(m & lanemask_lt());
+            L.ocol[p] = c;
+            L.oval[p] = val[t];
+        }
+        n_own += __popcll(m);
+    }
+    wave_sync();
+    // per own column: its rank among the own columns, the mirrored entries
+    // before it, and whether it is mirrored too (then its value gains the
+    // mirrored addend, after the own one)
+    // (four columns per LDS read: entries past n_own are padded with INT32_MAX)
+    for (int u = n_own + l; u < ((n_own + 3) & ~3); u += WAVE) L.ocol[u] = INT32_MAX;
+    wave_sync();
+    for (int u = l; u < n_own; u += WAVE) {
+        const int32_t c = L.ocol[u];
+        int r = 0;
+        const int4* oc4 = reinterpret_cast<const int4*>(L.ocol);
+        for (int v = 0; v < (n_own + 3) >> 2; ++v) {
+            const int4 q = oc4[v];
+            r += (q.x < c) + (q.y < c) + (q.z < c) + (q.w < c);
+        }
+        const int lb = in_lds ? lower_lds(L.cache, n_in, c) : lower_src(mk, n_in, c);
+        L.orank[u] = r;
+        const bool both = lb < n_in && (in_lds ? L.cache[lb] : (int32_t)(uint32_t)mk[lb]) == c;
+        L.olb[u] = lb;
+        if (both) L.oval[u] += __uint_as_float(pv[m0 + lb]);
+        L.scol[r] = c;
+        L.mpref[r] = both ? 1 : 0;
+    }
+    wave_sync();
+    // mpref: exclusive prefix count of the columns in both, by rank
+    int carry = 0;
+    for (int r0 = 0; r0 <= n_own; r0 += WAVE) {
+        const int r = r0 + l;
+        const int f = r < n_own ? L.mpref[r] : 0;
+        const int incl = (int)wave_incl_scan((uint32_t)f);
+        wave_sync();
+        if (r <= n_own) L.mpref[r] = carry + incl - f;
+        carry += __shfl(incl, WAVE - 1, WAVE);
+        wave_sync();
+    }
+    const int64_t o = row_ptr[i];
+    // own entries: (own before) + (mirrored before) - (in both before)
+    for (int u = l; u < n_own; u += WAVE) {
+        const int32_t c = L.ocol[u];
+        const int r = L.orank[u];
+        const int64_t pos = o + r + L.olb[u] - L.mpref[r];
+        if (pos < cap) {  // always true: the guard keeps every store in bounds
+            out_col[pos] = c;
+            out_val[pos] = L.oval[u] * inv_norm;
+        }
+    }
+    // mirrored entries that are not own ones
+    for (int x = l; x < n_in; x += WAVE) {
+        const int32_t c = in_lds ? L.cache[x] : (int32_t)(uint32_t)mk[x];
+        const int lb = lower_lds(L.scol, n_own, c);
+        if (!(lb < n_own && L.scol[lb] == c)) {
+            const int64_t pos = o + x + lb - L.mpref[lb];
+            if (pos < cap) {
+                out_col[pos] = c;
+                out_val[pos] = __uint_as_float(pv[m0 + x]) * inv_norm;
             }
-            if (e == a.n - 1)  // rows after the last stored row are empty
-                for (int64_t r = row + 1; r < a.N; ++r) a.row_ptr[r] = pos;
         }
     }
 }
 
-__global__ __launch_bounds__(256) void sym_zero_rows(int64_t* __restrict__ row_ptr, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < n) row_ptr[i] = 0;
-}
-
 struct SymPlan {
-    int64_t N, nnz_in, n2, nb;
-    int b;  // bits per index
+    int64_t N, nnz_in;
+    int col_bits;  // bits of a column index, N < 2^col_bits
     size_t sort_bytes, total;
 };
 
 static void sym_plan(int64_t N, int64_t nnz_in, SymPlan& p) {
     p.N = N;
     p.nnz_in = nnz_in;
-    p.n2 = 2 * nnz_in;
-    p.nb = std::max<int64_t>(1, ceil_div(p.n2, SYM_BLOCK));
-    p.b = N > 1 ? 64 - __builtin_clzll((unsigned long long)(N - 1)) : 1;
-    p.sort_bytes = 0;
-    rocprim::double_buffer<uint64_t> kb(nullptr, nullptr);
-    rocprim::double_buffer<float> vb(nullptr, nullptr);
-    (void)rocprim::radix_sort_pairs<SymSortConfig>(nullptr, p.sort_bytes, kb, vb, (size_t)std::max<int64_t>(p.n2, 1), 0,
-                                    (unsigned)(2 * p.b + 1));
-    p.sort_bytes = std::max<size_t>(p.sort_bytes, 1);
-    const int64_t n2 = std::max<int64_t>(p.n2, 1);
+    p.col_bits = 1;
+    while (((int64_t)1 << p.col_bits) <= N) ++p.col_bits;  // column N (ignored entries) fits too
+    const int64_t E = std::max<int64_t>(nnz_in, 1);
+    p.sort_bytes = sort_u64_temp_bytes(E);
+    const int64_t nb = ceil_div(std::max<int64_t>(N, 1), SYM_SCAN_BLOCK);
     Arena a;
-    a.take<uint64_t>(n2);        // keys (ping)
-    a.take<uint64_t>(n2);        // keys (pong)
-    a.take<float>(n2);           // values (ping)
-    a.take<float>(n2);           // values (pong)
-    a.take<int64_t>(p.nb);       // block offsets
-    a.take<char>(p.sort_bytes);  // radix sort temporary storage
+    a.take<uint64_t>(E);         // packed keys
+    a.take<uint32_t>(E);         // their values
+    a.take<uint64_t>(E);         // sorted keys
+    a.take<uint32_t>(E);         // sorted values
+    a.take<char>(p.sort_bytes);  // sort scratch
+    a.take<int64_t>(N + 1);      // column runs
+    a.take<int64_t>(N);          // distinct counts per row
+    a.take<int64_t>(nb + 1);     // scan block sums / offsets
+    a.take<int64_t>(nb + 1);
+    a.take<int32_t>(64);         // error flag
     p.total = a.used;
 }
 
 static atsne_status sym_run(const SymPlan& p, RowsIn rin, const int32_t* in_col, const float* in_val,
                             int64_t* row_ptr, int32_t* col, float* val, int64_t* nnz_host, void* wsp,
                             hipStream_t st) {
+    ATSNE_REQUIRE(p.nnz_in < (int64_t)UINT32_MAX, ATSNE_E_INVALID_ARG, "%lld conditional entries: at most 2^32 - 1",
+                  (long long)p.nnz_in);
     Arena a(wsp, p.total);
-    const int64_t n2 = std::max<int64_t>(p.n2, 1);
-    uint64_t* k0 = a.take<uint64_t>(n2);
-    uint64_t* k1 = a.take<uint64_t>(n2);
-    float* v0 = a.take<float>(n2);
-    float* v1 = a.take<float>(n2);
-    int64_t* bsum = a.take<int64_t>(p.nb);
+    const int64_t N = p.N, E = p.nnz_in;
+    const int64_t Ec = std::max<int64_t>(E, 1);
+    const int64_t nb = ceil_div(std::max<int64_t>(N, 1), SYM_SCAN_BLOCK);
+    uint64_t* k0 = a.take<uint64_t>(Ec);
+    uint32_t* v0 = a.take<uint32_t>(Ec);
+    uint64_t* k1 = a.take<uint64_t>(Ec);
+    uint32_t* v1 = a.take<uint32_t>(Ec);
     void* sort_tmp = a.take<char>(p.sort_bytes);
-    const int64_t N = p.N;
+    int64_t* runs = a.take<int64_t>(N + 1);
+    int64_t* cnt = a.take<int64_t>(N);
+    int64_t* bsum = a.take<int64_t>(nb + 1);
+    int64_t* boff = a.take<int64_t>(nb + 1);
+    int32_t* err = a.take<int32_t>(64);
+    const dim3 rows4((unsigned)ceil_div(N, 4)), blk(256);
     ProfScope ps_("sym_total", st);
-    if (p.n2 == 0) {
-        sym_zero_rows<<<dim3((unsigned)ceil_div(N + 1, 256)), dim3(256), 0, st>>>(row_ptr, N + 1);
-        ATSNE_LAUNCH_CHECK();
-    } else {
-        const int s = p.b + 1;
-        sym_keys<<<dim3((unsigned)ceil_div(N, 4)), dim3(256), 0, st>>>(rin, in_col, in_val, N, s,
-                                                                       reinterpret_cast<ulonglong2*>(k0),
-                                                                       reinterpret_cast<float2*>(v0));
-        ATSNE_LAUNCH_CHECK();
-        rocprim::double_buffer<uint64_t> kb(k0, k1);
-        rocprim::double_buffer<float> vb(v0, v1);
-        size_t sort_bytes = p.sort_bytes;
-        ATSNE_HIP(rocprim::radix_sort_pairs<SymSortConfig>(sort_tmp, sort_bytes, kb, vb, (size_t)p.n2, 0, (unsigned)(2 * p.b + 1),
-                                            st));
-        const uint64_t* K = kb.current();
-        const float* V = vb.current();
-        sym_heads<<<dim3((unsigned)p.nb), dim3(256), 0, st>>>(K, p.n2, bsum);
-        ATSNE_LAUNCH_CHECK();
-        sym_scan_blocks<<<dim3(1), dim3(1024), 0, st>>>(bsum, p.nb, row_ptr + N);
-        ATSNE_LAUNCH_CHECK();
-        EmitArgs e{K, V, p.n2, N, s, (1ull << p.b) - 1, bsum, (float)(1.0 / (2.0 * (double)N)), row_ptr, col, val};
-        sym_emit<<<dim3((unsigned)p.nb), dim3(256), 0, st>>>(e);
-        ATSNE_LAUNCH_CHECK();
-    }
+    sym_zero<<<dim3(1), dim3(64), 0, st>>>(err, 64);
+    ATSNE_LAUNCH_CHECK();
+    sym_pack<<<rows4, blk, 0, st>>>(rin, in_col, in_val, N, k0, v0);
+    ATSNE_LAUNCH_CHECK();
+    ATSNE_TRY(sort_pairs_u64(sort_tmp, p.sort_bytes, k0, v0, k1, v1, E, st, 32, 32 + p.col_bits));
+    sym_runs<<<dim3((unsigned)ceil_div(E + 1, 256)), blk, 0, st>>>(k1, E, N, runs);
+    ATSNE_LAUNCH_CHECK();
+    sym_row_count<<<rows4, blk, 0, st>>>(rin, in_col, N, k1, runs, cnt, err);
+    ATSNE_LAUNCH_CHECK();
+    sym_block_sums<<<dim3((unsigned)nb), dim3(1024), 0, st>>>(cnt, N, bsum);
+    ATSNE_LAUNCH_CHECK();
+    sym_scan_small<<<dim3(1), dim3(1024), 0, st>>>(bsum, nb, boff);
+    ATSNE_LAUNCH_CHECK();
+    sym_block_scan<<<dim3((unsigned)nb), dim3(1024), 0, st>>>(cnt, N, boff, row_ptr);
+    ATSNE_LAUNCH_CHECK();
+    const float inv = (float)(1.0 / (2.0 * (double)N));
+    if (rin.ptr == nullptr && rin.k <= 128)
+        sym_row_emit<128, 1024><<<rows4, blk, 0, st>>>(rin, in_col, in_val, N, k1, v1, runs, row_ptr, inv, 2 * E, col,
+                                                        val);
+    else if (rin.ptr == nullptr && rin.k <= 256)
+        sym_row_emit<256, 1024><<<rows4, blk, 0, st>>>(rin, in_col, in_val, N, k1, v1, runs, row_ptr, inv, 2 * E, col,
+                                                        val);
+    else
+        sym_row_emit<SYM_OWN_MAX, 512><<<rows4, blk, 0, st>>>(rin, in_col, in_val, N, k1, v1, runs, row_ptr, inv,
+                                                               2 * E, col, val);
+    ATSNE_LAUNCH_CHECK();
+    int32_t h_err = 0;
     ATSNE_HIP(hipMemcpyAsync(nnz_host, row_ptr + N, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    ATSNE_HIP(hipMemcpyAsync(&h_err, err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     ps_.stop();
     ATSNE_HIP(hipStreamSynchronize(st));
+    ATSNE_REQUIRE(h_err == 0, ATSNE_E_INVALID_ARG, "a conditional row holds more than %d entries", SYM_OWN_MAX);
     return ATSNE_OK;
 }
 
@@ -270,7 +413,8 @@ static atsne_status sym_run(const SymPlan& p, RowsIn rin, const int32_t* in_col,
 // copy is looked up once with hipGetSymbolAddress (with that device current)
 // and that address is what the kernels receive.  Calls on one GPU share its
 // copy, so calls that overlap on one GPU race; every kernel overwrites what
-// it reads, so the previous call's contents need no clearing.
+// it reads (the error flag is cleared by a kernel), so the previous call's
+// contents need no clearing.
 constexpr size_t SYM_NOALLOC_SCRATCH = (size_t)64 << 20;
 static __device__ __align__(256) unsigned char scratch[SYM_NOALLOC_SCRATCH];
 
@@ -302,6 +446,7 @@ extern "C" atsne_status atsne_symmetrize_noalloc(const int32_t* nbr_idx, const f
     ATSNE_REQUIRE(nbr_idx && P_cond && row_ptr && col && val && nnz_host, ATSNE_E_INVALID_ARG, "null pointer");
     ATSNE_REQUIRE(N >= 1 && N < (1ll << 31), ATSNE_E_INVALID_ARG, "N=%lld out of range", (long long)N);
     ATSNE_REQUIRE(k >= 1 && k <= N - 1, ATSNE_E_K_RANGE, "k=%d out of [1, N-1]", k);
+    ATSNE_REQUIRE(k <= SYM_OWN_MAX, ATSNE_E_K_RANGE, "k=%d above %d", k, SYM_OWN_MAX);
     SymPlan p;
     sym_plan(N, N * (int64_t)k, p);
     ATSNE_REQUIRE(p.total <= SYM_NOALLOC_SCRATCH, ATSNE_E_NOMEM,
@@ -331,6 +476,7 @@ extern "C" atsne_status atsne_symmetrize(const int32_t* nbr_idx, const float* P_
     ATSNE_REQUIRE(nbr_idx && P_cond && row_ptr && col && val && nnz_host, ATSNE_E_INVALID_ARG, "null pointer");
     ATSNE_REQUIRE(N >= 1 && N < (1ll << 31), ATSNE_E_INVALID_ARG, "N=%lld out of range", (long long)N);
     ATSNE_REQUIRE(k >= 1 && k <= N - 1, ATSNE_E_K_RANGE, "k=%d out of [1, N-1]", k);
+    ATSNE_REQUIRE(k <= SYM_OWN_MAX, ATSNE_E_K_RANGE, "k=%d above %d", k, SYM_OWN_MAX);
     SymPlan p;
     sym_plan(N, N * (int64_t)k, p);
     hipStream_t st = static_cast<hipStream_t>(stream);

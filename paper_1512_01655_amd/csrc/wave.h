@@ -97,6 +97,22 @@ __device__ __forceinline__ uint64_t pack_key(float d, int32_t j) {
 __device__ __forceinline__ float key_dist(uint64_t k) { return ord2f((uint32_t)(k >> 32)); }
 __device__ __forceinline__ int32_t key_index(uint64_t k) { return (int32_t)(uint32_t)k; }
 
+// Stable multi-split of one wave's elements by an 8-bit digit: for each
+// active lane, the number of active lanes below it with the same digit
+// (rank) and the number of active lanes with that digit (count).  Eight
+// ballots narrow the set of peer lanes one digit bit at a time.
+__device__ __forceinline__ void wave_digit_rank(bool active, uint32_t digit, int& rank, int& count) {
+    uint64_t peers = ballot(active);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const bool bit = (digit >> b) & 1u;
+        const uint64_t m = ballot(active && bit);
+        peers &= bit ? m : ~m;
+    }
+    rank = __popcll(peers & lanemask_lt());
+    count = __popcll(peers);
+}
+
 // Radix selection by one wave: returns the key of 1-based rank `rank` among
 // the keys that `for_each` feeds (each lane visits its own share; keys are
 // distinct).  8-bit digits from the top; stops as soon as the rank's bucket

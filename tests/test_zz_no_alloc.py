@@ -63,12 +63,22 @@ def test_noalloc_equals_allocating_entry_point():
         say("    nnz %d, identical" % n1)
 
 
+SCRATCH_BYTES = 64 << 20  # the allocation-free symmetrisation's device array
+
+
 def test_noalloc_refuses_inputs_beyond_its_scratch():
     A = lib()
     L = A.load()
+    N, k = 100000, 90
+    # the refusal happens on the host before any work: the input must need
+    # more scratch than the array holds, or the call would run its kernels on
+    # the placeholder buffers below
+    b = ctypes.c_size_t()
+    assert L.atsne_symmetrize_workspace_size(N, N * k, ctypes.byref(b)) == A.OK
+    assert b.value > 2 * SCRATCH_BYTES
     dummy = torch.zeros(16, dtype=torch.int32, device="cuda")
     nnz = ctypes.c_int64(-1)
     p = ctypes.c_void_p(dummy.data_ptr())
-    s = L.atsne_symmetrize_noalloc(p, p, 20000, 90, p, p, p, ctypes.byref(nnz), None)
+    s = L.atsne_symmetrize_noalloc(p, p, N, k, p, p, p, ctypes.byref(nnz), None)
     assert s == A.E_NOMEM and b"allocation-free" in L.atsne_last_error()
     assert nnz.value == -1
