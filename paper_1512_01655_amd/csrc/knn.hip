@@ -41,23 +41,23 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 
-// Workgroup geometry per contraction type: FP32 and BF16 run 8 waves (256
-// queries x 256 keys, two waves per SIMD so one wave's epilogue and LDS
-// waits hide behind the other's MFMAs); FP8 keeps 4 waves (128 x 256) at one
-// wave per SIMD, where its scaled MFMAs fit the 512-register budget.  The
+// Workgroup geometry: every contraction type runs 8 waves (256 queries x 256
+// keys), two waves per SIMD, so one wave's epilogue (filter, appends) and LDS
+// waits hide behind the other's MFMAs.  For FP8 this costs a few spilled
+// registers per lane and still beats one wave per SIMD by a third.  The
 // small geometry (FP32/BF16, 4 waves, 128 queries x 128 keys, two
 // workgroups per CU) gives small problems four times as many workgroups.
 template <int P, bool SMALL = false>
 struct TileGeom {
-    static constexpr int WAVES = (SMALL || P == ATSNE_PREC_FP8_E4M3) ? 4 : 8;
+    static constexpr int WAVES = SMALL ? 4 : 8;
     static constexpr int THREADS = 64 * WAVES;
     static constexpr int QB = 32 * WAVES;  // queries per workgroup
     static constexpr int KT = SMALL ? 128 : 256;  // keys per tile
     static constexpr int NKB = KT / 32;          // MFMA key blocks per tile
-    static constexpr int WPE = P == ATSNE_PREC_FP8_E4M3 ? 1 : 2;
+    static constexpr int WPE = 2;
 };
 constexpr int KNN_XCDS = 8;  // accelerator complex dies; workgroups go round-robin over them
-__host__ __device__ constexpr int qb_of(int prec) { return prec == ATSNE_PREC_FP8_E4M3 ? 128 : 256; }
+__host__ __device__ constexpr int qb_of(int) { return 256; }
 constexpr int KT = KNN_KT;      // keys per tile (8 MFMA blocks of 32)
 constexpr int NKB = KT / 32;    // key blocks per tile
 constexpr int CHUNK_UNITS = 8;  // 16-byte units per row per D-chunk (128 bytes)
