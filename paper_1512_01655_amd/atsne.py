@@ -18,7 +18,7 @@ LIBPATH = _HERE / "libatsne.so"
 
 OK, E_INVALID_ARG, E_K_RANGE, E_NOMEM, E_HIP, E_NOT_CONVERGED, E_BUSY, E_UNSUPPORTED = range(8)
 PREC = {"fp32": 0, "bf16": 1, "fp8": 2, "fp8_e4m3": 2, "fp32x3": 3}
-FLAG_FP64_RERANKED, FLAG_NOT_CONVERGED, FLAG_DEGENERATE, FLAG_EXACT_SCAN = 1, 2, 4, 8
+FLAG_FP64_RERANKED, FLAG_NOT_CONVERGED, FLAG_DEGENERATE, FLAG_EXACT_SCAN, FLAG_TOL_LIMITED = 1, 2, 4, 8, 16
 
 # symbols declared by include/atsne.h
 EXPORTS = [

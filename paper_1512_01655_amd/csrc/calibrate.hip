@@ -130,9 +130,13 @@ __global__ __launch_bounds__(256) void calibrate_rows(const float* __restrict__ 
         }
         float mid = hi;
         bool done = fabsf(h - target) <= htol;
+        bool collapsed = false;
         for (; !done && it < max_iter; ++it) {
             mid = 0.5f * (lo + hi);
-            if (!(mid > lo && mid < hi)) break;  // bracket collapsed to adjacent floats
+            if (!(mid > lo && mid < hi)) {  // bracket collapsed to adjacent floats
+                collapsed = true;
+                break;
+            }
             h = entropy(mid, Z);
             if (fabsf(h - target) <= htol) break;
             if (h > target)
@@ -140,7 +144,10 @@ __global__ __launch_bounds__(256) void calibrate_rows(const float* __restrict__ 
             else
                 hi = mid;
         }
-        if (it >= max_iter) fl |= ATSNE_FLAG_NOT_CONVERGED;
+        if (it >= max_iter)
+            fl |= ATSNE_FLAG_NOT_CONVERGED;
+        else if (collapsed)
+            fl |= ATSNE_FLAG_TOL_LIMITED;  // no FP32 beta meets tol: the entropy's rounding decides
         b = mid;
         h = entropy(b, Z);  // weights of the returned beta
     }

@@ -41,11 +41,14 @@ def _check_cal(A, ora, d2, mu):
     say("    max|dP| %.3g  max|perp-mu| %.3g  max rel dbeta %.3g" % (
         dP, np.abs(perp - mu).max(), (np.abs(gb - ob) / ob)[ok].max()))
     assert dP <= parity.P_TOL
-    # FP32 resolution of beta bounds the perplexity error near 1e-6 relative;
-    # the 1e-4 contract is for the paper's perplexities (mu <= 50).
+    # the FP32 entropy resolves the perplexity to about 1e-6 mu: the 1e-4
+    # contract holds up to mu = 100, 2e-6 mu above (the bound the entry
+    # states); rows whose bracket collapsed before tol carry TOL_LIMITED
+    lim = (gfl[ok] & A.FLAG_TOL_LIMITED) != 0
+    say("    TOL_LIMITED rows %d / %d" % (int(lim.sum()), int(ok.sum())))
     assert np.abs(perp - mu).max() <= (parity.PERP_TOL if mu <= 100 else 2e-6 * mu)
     assert np.abs(gP.astype(np.float64).sum(1) - 1.0).max() <= 1e-6
-    assert np.all(gfl[ok] == 0)
+    assert np.all((gfl[ok] | A.FLAG_TOL_LIMITED) == A.FLAG_TOL_LIMITED)
     return gP, gb
 
 
