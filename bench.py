@@ -44,6 +44,13 @@ def parse():
                          "copy (the reference kernel for scaling HBM byte counters); prints the launch shapes")
     ap.add_argument("--serve-rate", type=float, default=25.0, help="Poisson request rate (req/s)")
     ap.add_argument("--serve-requests", type=int, default=120)
+    ap.add_argument("--serve-sweep", default=None,
+                    help="comma-separated rates (req/s): only the serving sweep, one JSON line per rate "
+                         "(--sweep-requests measured after --sweep-warmup)")
+    ap.add_argument("--sweep-requests", type=int, default=2000)
+    ap.add_argument("--sweep-warmup", type=int, default=100)
+    ap.add_argument("--sweep-insert-points", default="64,4096",
+                    help="inclusive range of points per insert request in the sweep (the survey's mix: 64,4096)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target length of the oracle sample")
     return ap.parse_args()
 
@@ -286,24 +293,34 @@ def approx_leg(A, torch, Xt, mu, k, exact_idx, exact_value, rho=0.9, C=256, iter
             "step": "cluster-pruned kNN + calibrate + symmetrize (build and fit excluded, reported apart)"}
 
 
-def serve_load(A, torch, X, rate, n_req, n_warm, seed=5):
+def serve_load(A, torch, X, rate, n_req, n_warm, seed=5, pool_cache=None, progress=0, insert_points=(64, 4096)):
     """Poisson stream against a server holding X: half inserts of 64-4096 new
     points (same generator, fresh noise), half refines of 1000-20000 resident
-    ids at perplexity 10, 30 or 50.  Latency = completion - submission."""
+    ids at perplexity 10, 30 or 50.  Latency = completion - the client's call.
+    The request sequence depends on the seed only, so runs at several rates
+    share it (and the insert pool, through pool_cache)."""
     import threading
 
     from paper_1512_01655_amd import datagen
 
     rng = np.random.default_rng(seed)
     kinds = rng.random(n_req) < 0.5
-    sizes = np.where(kinds, rng.integers(64, 4097, n_req), rng.integers(1000, 20001, n_req))
+    sizes = np.where(kinds, rng.integers(insert_points[0], insert_points[1] + 1, n_req),
+                     rng.integers(1000, 20001, n_req))
     mus = rng.choice([10.0, 30.0, 50.0], n_req)
     gaps = rng.exponential(1.0 / rate, n_req)
     n_new = int(sizes[kinds].sum())
-    pool = torch.from_numpy(datagen.image_like(n=max(n_new, 1), noise_seed=seed + 1000)).cuda()
+    key = (seed, n_req, tuple(insert_points))
+    if pool_cache is not None and key in pool_cache:
+        pool = pool_cache[key]
+    else:
+        pool = torch.from_numpy(datagen.image_like(n=max(n_new, 1), noise_seed=seed + 1000)).cuda()
+        if pool_cache is not None:
+            pool_cache[key] = pool
     srv = A.Server(torch.from_numpy(X).cuda(), 30.0, capacity_rows=X.shape[0] + n_new + 1)
     rids, lat, rows = [], [], []
     done = threading.Event()
+    t0 = time.perf_counter()
 
     def collect():
         i = 0
@@ -317,6 +334,9 @@ def serve_load(A, torch, X, rate, n_req, n_warm, seed=5):
             rows.append(r["n_rows"])
             srv.release(rids[i])
             i += 1
+            if progress and i % progress == 0:
+                log("  serve %.0f req/s: %d / %d complete, %.0f s, last latency %.0f ms" % (
+                    rate, i, n_req, time.perf_counter() - t0, lat[-1]))
         done.set()
 
     th = threading.Thread(target=collect)
@@ -347,13 +367,21 @@ def serve_load(A, torch, X, rate, n_req, n_warm, seed=5):
     srv.close()
     lat_m = np.array(lat[n_warm:])
     rows_m = np.array(rows[n_warm:])
+    kind_m = kinds[n_warm:]
     span = t_end - t_first
+
+    def pct(a, q):
+        return round(float(np.percentile(a, q)), 2) if len(a) else None
+
     return {
         "rate_req_s": rate, "requests": n_req - n_warm, "warmup_requests": n_warm,
-        "p50_ms": round(float(np.percentile(lat_m, 50)), 2), "p99_ms": round(float(np.percentile(lat_m, 99)), 2),
+        "p50_ms": pct(lat_m, 50), "p99_ms": pct(lat_m, 99),
+        "insert_p50_ms": pct(lat_m[kind_m], 50), "insert_p99_ms": pct(lat_m[kind_m], 99),
+        "refine_p50_ms": pct(lat_m[~kind_m], 50), "refine_p99_ms": pct(lat_m[~kind_m], 99),
         "mean_ms": round(float(lat_m.mean()), 2), "throughput_req_s": round((n_req - n_warm) / span, 2),
+        "arrival_span_s": round(float(gaps[n_warm:].sum()), 1), "measured_span_s": round(span, 1),
         "rows_per_s": round(float(rows_m.sum()) / span, 1),
-        "mix": "0.5 insert (64-4096 points) / 0.5 refine (1000-20000 ids, mu in {10,30,50})",
+        "mix": "0.5 insert (%d-%d points) / 0.5 refine (1000-20000 ids, mu in {10,30,50})" % tuple(insert_points),
         "corpus_rows_start": int(X.shape[0]), "corpus_rows_end": int(st["corpus_rows"]),
         "launches": int(st["launches"]), "max_requests_per_launch": int(st["max_requests_per_launch"]),
         "max_concurrent": int(st["max_concurrent"]),
@@ -466,6 +494,18 @@ def main():
     from paper_1512_01655_amd import datagen
 
     A.load()
+    if a.serve_sweep:
+        X = datagen.image_like()
+        cache = {}
+        for rate in [float(v) for v in a.serve_sweep.split(",")]:
+            log("serve sweep: %.0f req/s, %d requests after %d warm-up ..." % (rate, a.sweep_requests,
+                                                                             a.sweep_warmup))
+            ins = tuple(int(v) for v in a.sweep_insert_points.split(","))
+            rec = serve_load(A, torch, X, rate, a.sweep_requests + a.sweep_warmup, a.sweep_warmup, pool_cache=cache,
+                             progress=100, insert_points=ins)
+            rec["scheduler"] = "launch-batched (host worker, continuous batching)"
+            print(json.dumps({"serve_sweep": rec}), flush=True)
+        return
     if a.workload == "imagelike":
         X = datagen.image_like()
         name = "imagelike_N70000_D784_mu30_k90"
