@@ -26,8 +26,17 @@ namespace atsne {
 
 constexpr uint32_t ORD_UNREACHED = 0xffffffffu;
 
+// Sort keys are (key code << ib) | index with ib = index_bits(N): only the
+// 32 + ib significant bits are sorted (five radix passes at N = 70000 instead
+// of seven over the whole word), and the order is that of (code, index).
+static int index_bits(int64_t N) {
+    int b = 1;
+    while (((int64_t)1 << b) < N) ++b;
+    return b;
+}
+
 __global__ __launch_bounds__(256) void ord_density_keys(const float* __restrict__ beta,
-                                                        const int32_t* __restrict__ ids, int64_t M, int64_t N,
+                                                        const int32_t* __restrict__ ids, int64_t M, int64_t N, int ib,
                                                         uint64_t* __restrict__ keys, int32_t* __restrict__ bad) {
     const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (m >= M) return;
@@ -37,13 +46,13 @@ __global__ __launch_bounds__(256) void ord_density_keys(const float* __restrict_
         keys[m] = ~0ull;
         return;
     }
-    keys[m] = ((uint64_t)f2ord(beta[id]) << 32) | (uint32_t)id;
+    keys[m] = ((uint64_t)f2ord(beta[id]) << ib) | (uint64_t)id;
 }
 
-__global__ __launch_bounds__(256) void ord_unpack(const uint64_t* __restrict__ keys, int64_t n,
+__global__ __launch_bounds__(256) void ord_unpack(const uint64_t* __restrict__ keys, int64_t n, int ib,
                                                   int32_t* __restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < n) out[i] = (int32_t)(uint32_t)keys[i];
+    if (i < n) out[i] = (int32_t)(keys[i] & (((uint64_t)1 << ib) - 1));
 }
 
 __global__ __launch_bounds__(256) void ord_init(int64_t N, uint32_t* __restrict__ dist, int32_t* __restrict__ stamp) {
@@ -91,14 +100,14 @@ __global__ __launch_bounds__(256) void ord_expand(const int32_t* __restrict__ fr
 }
 
 // Keys of the reached points, and the per-point key as a float (+inf: unreached).
-__global__ __launch_bounds__(256) void ord_collect(const uint32_t* __restrict__ dist, int64_t N, int weighted,
+__global__ __launch_bounds__(256) void ord_collect(const uint32_t* __restrict__ dist, int64_t N, int weighted, int ib,
                                                    float* __restrict__ key_out, uint64_t* __restrict__ keys,
                                                    int32_t* __restrict__ n_keys) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= N) return;
     const uint32_t d = dist[i];
     if (key_out) key_out[i] = d == ORD_UNREACHED ? INFINITY : (weighted ? __uint_as_float(d) : (float)d);
-    if (d != ORD_UNREACHED) keys[atomicAdd(n_keys, 1)] = ((uint64_t)d << 32) | (uint32_t)i;
+    if (d != ORD_UNREACHED) keys[atomicAdd(n_keys, 1)] = ((uint64_t)d << ib) | (uint64_t)i;
 }
 
 static unsigned blocks(int64_t n) { return (unsigned)std::max<int64_t>(1, ceil_div(n, 256)); }
@@ -130,10 +139,10 @@ static size_t order_ws(int64_t N, void* base, OrderWs* w) {
     return a.used;
 }
 
-static atsne_status sort_and_unpack(OrderWs& w, int64_t n, int32_t* out, hipStream_t st) {
+static atsne_status sort_and_unpack(OrderWs& w, int64_t n, int ib, int32_t* out, hipStream_t st) {
     if (n == 0) return ATSNE_OK;
-    ATSNE_TRY(sort_u64(w.sort_tmp, w.sort_bytes, w.keys_in, w.keys_out, n, st));
-    ord_unpack<<<blocks(n), 256, 0, st>>>(w.keys_out, n, out);
+    ATSNE_TRY(sort_u64(w.sort_tmp, w.sort_bytes, w.keys_in, w.keys_out, n, st, 0, 32 + ib));
+    ord_unpack<<<blocks(n), 256, 0, st>>>(w.keys_out, n, ib, out);
     ATSNE_LAUNCH_CHECK();
     return ATSNE_OK;
 }
@@ -168,9 +177,10 @@ extern "C" atsne_status atsne_order_density(const float* beta, int64_t N, const 
     OrderWs w;
     order_ws(M, sc.ptr, &w);
     ATSNE_HIP(hipMemsetAsync(w.counters, 0, sizeof(int32_t) * 4, st));
-    ord_density_keys<<<blocks(M), 256, 0, st>>>(beta, ids, M, N, w.keys_in, w.counters);
+    const int ib = index_bits(N);
+    ord_density_keys<<<blocks(M), 256, 0, st>>>(beta, ids, M, N, ib, w.keys_in, w.counters);
     ATSNE_LAUNCH_CHECK();
-    ATSNE_TRY(sort_and_unpack(w, M, order_out, st));
+    ATSNE_TRY(sort_and_unpack(w, M, ib, order_out, st));
     if (ids) {
         int32_t bad = 0;
         ATSNE_TRY(read_counter(w.counters, &bad, st));
@@ -225,11 +235,12 @@ extern "C" atsne_status atsne_order_neighbourhood(const int32_t* nbr_idx, const 
         std::swap(front, next);
         n_front = nn;
     }
-    ord_collect<<<blocks(N), 256, 0, st>>>(w.dist, N, weighted, key_out, w.keys_in, w.counters + 3);
+    const int ib = index_bits(N);
+    ord_collect<<<blocks(N), 256, 0, st>>>(w.dist, N, weighted, ib, key_out, w.keys_in, w.counters + 3);
     ATSNE_LAUNCH_CHECK();
     int32_t reached = 0;
     ATSNE_TRY(read_counter(w.counters + 3, &reached, st));
-    ATSNE_TRY(sort_and_unpack(w, reached, order_out, st));
+    ATSNE_TRY(sort_and_unpack(w, reached, ib, order_out, st));
     *n_reached_host = reached;
     return ATSNE_OK;
 }
