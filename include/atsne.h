@@ -123,7 +123,8 @@ atsne_status atsne_knn(const float* X, int64_t N, int32_t D, int64_t ld, atsne_p
 
 /* As atsne_knn for the M query rows query_ids[0..M) (device int32, each in
  * [0, N)) of the corpus X[0..N); each query excludes itself.  Outputs are
- * [M x k] and [M].  This is the per-point exact refinement of Sec. 4.3
+ * [M x k] and [M]; with M = 0 the call checks its sizes and returns, and
+ * query_ids and the outputs may be NULL.  This is the per-point exact refinement of Sec. 4.3
  * applied to a selection (Sec. 5.1). */
 atsne_status atsne_knn_subset(const float* X, int64_t N, int32_t D, int64_t ld, const int32_t* query_ids,
                               int64_t M, atsne_precision prec, int32_t k, int32_t k_cand, int32_t* nbr_idx,

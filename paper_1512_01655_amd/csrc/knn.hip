@@ -2264,7 +2264,7 @@ static atsne_status knn_impl(const float* X, int64_t N, int32_t D, int64_t ld, c
                              atsne_precision prec, int32_t k, int32_t k_cand, int32_t* nbr_idx, float* nbr_d2,
                              float* nbr_d2_lo, uint8_t* flags, void* ws, size_t ws_bytes, void* stream) {
     clear_error();
-    ATSNE_REQUIRE(X && nbr_idx && nbr_d2, ATSNE_E_INVALID_ARG, "null X or output pointer");
+    ATSNE_REQUIRE(X && (M == 0 || (nbr_idx && nbr_d2)), ATSNE_E_INVALID_ARG, "null X or output pointer");
     ATSNE_REQUIRE(ld >= D, ATSNE_E_INVALID_ARG, "ld=%lld < D=%d", (long long)ld, D);
     KnnPlan p;
     ATSNE_TRY(make_plan(N, M, D, (int)prec, k, k_cand, p));

@@ -207,6 +207,25 @@ def test_knn_subset_repeated_ids(A, prec):
     assert np.array_equal(idx, f_idx[q]) and np.array_equal(d2, f_d2[q])
 
 
+@pytest.mark.parametrize("prec", EXACT)
+@pytest.mark.parametrize("N,D,k,kc", [(2, 5, 1, 0), (3, 2, 2, 0), (500, 1, 90, 0), (260, 65536, 10, 0),
+                                      (1100, 16, 1000, 1024)])
+def test_knn_extremes(A, ora, N, D, k, kc, prec):
+    # the entry's limits: the fewest rows (N = 2, 3), one dimension (D = 1:
+    # near ties everywhere), the largest D (65536: 2048 chunks per tile), the
+    # largest k (1000) with the largest candidate count (1024)
+    X = np.random.default_rng(N + D).normal(size=(N, D)).astype(np.float32)
+    _compare(A, ora, X, k, prec=prec, kc=kc)
+
+
+@pytest.mark.parametrize("prec", EXACT + ["bf16", "fp8"])
+def test_knn_subset_empty(A, prec):
+    # no query rows: empty outputs, nothing launched that reads them
+    X = datagen.mixture_isotropic(n=600, d=20)
+    idx, d2, fl = run_knn(A, X, 10, prec, qids=np.zeros(0, np.int32))
+    assert idx.shape == (0, 10) and d2.shape == (0, 10) and fl.shape == (0,)
+
+
 def test_knn_errors(A):
     import torch
 
