@@ -116,7 +116,19 @@ atsne_status atsne_knn_workspace_size(int64_t N, int64_t M, int32_t D, atsne_pre
  *   flags    [N] uint8 out (may be NULL): ATSNE_FLAG_FP64_RERANKED,
  *            ATSNE_FLAG_EXACT_SCAN.
  * Self is excluded by index; exact duplicates are neighbours at distance 0;
- * equal distances are ordered by the lower index.  Asynchronous. */
+ * equal distances are ordered by the lower index.  Asynchronous, except a
+ * seeded search (below), which synchronises the stream.
+ * Seeding (ATSNE_PREC_FP8_E4M3, N >= 2^18 contiguous rows, ld == D): the
+ *   search first bounds each row's k_cand-th smallest key code from the
+ *   keys near it (a k-means partition of about N/1000 clusters, the row's
+ *   own cluster and its 7 nearest searched with the same FP8 tile), so its
+ *   tiles keep about k_cand keys per row from the start instead of every
+ *   key below a threshold that tightens as the corpus streams past.  The
+ *   outputs are those of the unseeded search bit for bit.  The pass
+ *   allocates its own device memory (about 9 GB at its peak for N = 10^6,
+ *   freed before the search) whatever ws is; ATSNE_FP8_SEED=0 in the
+ *   environment turns it off.
+ */
 atsne_status atsne_knn(const float* X, int64_t N, int32_t D, int64_t ld, atsne_precision prec, int32_t k,
                        int32_t k_cand, int32_t* nbr_idx, float* nbr_d2, float* nbr_d2_lo, uint8_t* flags, void* ws,
                        size_t ws_bytes, void* stream);

@@ -111,5 +111,11 @@ struct ProfScope {
     ~ProfScope() { stop(); }
     void stop();  // records the end event now (idempotent)
 };
+// While one is alive on this thread, ProfScopes record nothing: a stage
+// reported as a whole (the FP8 seeding pass) hides the kernels inside it.
+struct ProfQuiet {
+    ProfQuiet();
+    ~ProfQuiet();
+};
 
 }  // namespace atsne

@@ -589,3 +589,116 @@ extern "C" atsne_status atsne_ivf_destroy(atsne_ivf* ix) {
     delete ix;
     return ATSNE_OK;
 }
+
+namespace atsne {
+
+// Seeding pass of a large FP8 search.  Any subset of a row's keys has a
+// kc-th smallest key code d' at least the row's kc-th smallest over all
+// keys, so the search may keep only keys at or below it from its first tile
+// on (Batch::tau_seed).  The subset here is the keys near the row: the
+// k-means partition of the approximate search (strided initial points, no
+// Lloyd step: Voronoi cells of about SEED_CLUSTER_ROWS points), the row's own
+// cluster and its nearest ones in probe order, searched in FP8 with the same
+// tile kernel, so every d' is bit for bit the one the full search computes.
+constexpr int64_t SEED_CLUSTER_ROWS = 1000;
+constexpr int SEED_PROBE = 8;               // clusters searched per point (extended to kc + 1 rows)
+constexpr int64_t SEED_BATCH_ROWS = 524288;  // rows per seeding launch (bounds the slot memory, ~3.8 GB)
+
+// The tiles of cluster_tiles, listed cluster by cluster in probe order (the
+// own cluster first): a row's threshold settles on its nearest keys within
+// a few tiles, so the later tiles append few keys.  The order changes no
+// result: a row's union still holds its kc smallest over all listed tiles.
+static std::vector<std::vector<int32_t>> seed_tiles(const atsne_ivf& ix, int n_probe, int k) {
+    const int C = ix.C;
+    std::vector<std::vector<int32_t>> out(C);
+    for (int c = 0; c < C; ++c) {
+        std::set<int32_t> cover;
+        int64_t rows = 0;
+        int used = 0;
+        for (int u = 0; u < C; ++u) {
+            if (used >= n_probe && rows >= k + 1) break;
+            ++used;
+            const int p = ix.probe[(size_t)c * C + u];
+            const int64_t lo = ix.start[p], hi = ix.start[p + 1];
+            if (hi <= lo) continue;
+            rows += hi - lo;
+            for (int64_t t = lo / IVF_TILE; t <= (hi - 1) / IVF_TILE; ++t)
+                if (cover.insert((int32_t)t).second) out[c].push_back((int32_t)t);
+        }
+    }
+    return out;
+}
+
+atsne_status fp8_seed_thresholds(const float* X, int64_t N, int32_t D, int64_t ld, int kc, float* tau,
+                                 hipStream_t st) {
+    ATSNE_REQUIRE(ld == D, ATSNE_E_UNSUPPORTED, "seeding needs contiguous rows");
+    const int C = (int)std::min<int64_t>(IVF_MAX_C, std::max<int64_t>(2, N / SEED_CLUSTER_ROWS));
+    std::vector<int32_t> init(C);
+    for (int c = 0; c < C; ++c) init[c] = (int32_t)((int64_t)c * N / C);
+    atsne_ivf* ixp = nullptr;
+    ATSNE_TRY(atsne_ivf_build(X, N, D, C, init.data(), 0, &ixp, st));
+    std::unique_ptr<atsne_ivf, atsne_status (*)(atsne_ivf*)> guard(ixp, atsne_ivf_destroy);
+    atsne_ivf& ix = *ixp;
+    // FP8 copy of the sorted corpus (per-row scales: the rows' FP8 codes,
+    // norms and scales equal those of the same rows in the caller's order)
+    const int64_t cap = ceil_div(N, (int64_t)KNN_KT) * KNN_KT;
+    DevBuf cm;
+    ATSNE_TRY(cm.get(corpus_bytes(ATSNE_PREC_FP8_E4M3, cap, D)));
+    Corpus c8;
+    corpus_bind(c8, ATSNE_PREC_FP8_E4M3, ix.Xperm, D, D, cap, cm.p);
+    ATSNE_TRY(corpus_prep(c8, 0, cap, N, st));
+    const auto tiles = seed_tiles(ix, SEED_PROBE, kc);
+    for (int c0 = 0; c0 < C;) {
+        int c1 = c0 + 1;
+        while (c1 < C && ix.start[c1 + 1] - ix.start[c0] <= SEED_BATCH_ROWS) ++c1;
+        std::vector<int32_t> clusters;
+        for (int c = c0; c < c1; ++c) clusters.push_back(c);
+        const Blocks b = make_blocks(ix, tiles, clusters);
+        const int64_t M = ix.start[c1] - ix.start[c0];
+        const int64_t nb = (int64_t)b.blk_q.size() - 1;
+        if (M > 0 && nb > 0) {
+            const SearchPlan p = plan_list_search(M, nb, kc, kc, 1);
+            Arena a;
+            a.take<char>(p.ws_bytes);
+            a.take<int32_t>(nb + 1);
+            a.take<int32_t>(nb + 1);
+            a.take<int32_t>(std::max<size_t>(b.tl.size(), 1));
+            a.take<int32_t>(M);
+            DevBuf buf;
+            ATSNE_TRY(buf.get(a.used));
+            Arena w(buf.p, a.used);
+            void* ws = w.take<char>(p.ws_bytes);
+            int32_t* d_blk_q = w.take<int32_t>(nb + 1);
+            int32_t* d_blk_t = w.take<int32_t>(nb + 1);
+            int32_t* d_tl = w.take<int32_t>(std::max<size_t>(b.tl.size(), 1));
+            int32_t* d_row_blk = w.take<int32_t>(M);
+            ATSNE_HIP(hipMemcpyAsync(d_blk_q, b.blk_q.data(), sizeof(int32_t) * (nb + 1), hipMemcpyHostToDevice, st));
+            ATSNE_HIP(hipMemcpyAsync(d_blk_t, b.blk_t.data(), sizeof(int32_t) * (nb + 1), hipMemcpyHostToDevice, st));
+            if (!b.tl.empty())
+                ATSNE_HIP(hipMemcpyAsync(d_tl, b.tl.data(), sizeof(int32_t) * b.tl.size(), hipMemcpyHostToDevice, st));
+            ATSNE_HIP(hipMemcpyAsync(d_row_blk, b.row_blk.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice, st));
+            Batch bt;
+            bt.M = M;
+            bt.qids = nullptr;
+            bt.m0 = ix.start[c0];  // batch row m is sorted row start[c0] + m
+            bt.nlim = N;
+            bt.key_lo = 0;
+            bt.k = kc;
+            bt.kc = kc;
+            bt.n_blocks = nb;
+            bt.blk_q = d_blk_q;
+            bt.blk_t = d_blk_t;
+            bt.tl_idx = d_tl;
+            bt.row_blk = d_row_blk;
+            bt.tau_out = tau;
+            bt.tau_map = ix.perm;  // sorted row -> the caller's row
+            ATSNE_TRY(knn_search(c8, bt, p, ws, st));
+            // host arrays and the device buffer must outlive the queued work
+            ATSNE_HIP(hipStreamSynchronize(st));
+        }
+        c0 = c1;
+    }
+    return ATSNE_OK;
+}
+
+}  // namespace atsne

@@ -30,6 +30,8 @@
 //                  scanned row ends exactly as a certified row would.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
+#include <memory>
 #include <type_traits>
 
 #include "knn_internal.h"
@@ -190,19 +192,26 @@ __global__ __launch_bounds__(256) void knn_prep(const float* __restrict__ X, int
 
 // Prefix maximum of the norms over [r0, r1), continuing from pmax[r0 - 1].
 // One workgroup walks the range in chunks of 1024 rows.
-__global__ __launch_bounds__(1024) void knn_pmax(const float* __restrict__ norms, float* __restrict__ pmax,
-                                                 int64_t r0, int64_t r1) {
+// Prefix max of the row norms over rows [r0, r1), continuing pmax[r0 - 1]:
+// (1) each workgroup the prefix within its PMAX_CHUNK rows and the chunk's
+// maximum, (2) one workgroup the exclusive prefix of the chunk maxima (the
+// carry into each chunk), (3) every row its chunk's carry.
+constexpr int PMAX_CHUNK = 4096;
+
+__global__ __launch_bounds__(1024) void knn_pmax_local(const float* __restrict__ norms, float* __restrict__ pmax,
+                                                       int64_t r0, int64_t r1, float* __restrict__ blk) {
     __shared__ float wmax[16];
     __shared__ float carry_s;
     const int t = threadIdx.x, l = t & 63, w = t >> 6;
-    if (t == 0) carry_s = r0 > 0 ? pmax[r0 - 1] : 0.0f;
+    const int64_t c0 = r0 + (int64_t)blockIdx.x * PMAX_CHUNK;
+    if (t == 0) carry_s = 0.0f;  // norms are non-negative
     __syncthreads();
-    for (int64_t base = r0; base < r1; base += 1024) {
-        const int64_t i = base + t;
+    for (int s = 0; s < PMAX_CHUNK / 1024; ++s) {
+        const int64_t i = c0 + 1024 * s + t;
         float v = i < r1 ? norms[i] : 0.0f;
 #pragma unroll
         for (int o = 1; o < WAVE; o <<= 1) {
-            float u = __shfl_up(v, o, WAVE);
+            const float u = __shfl_up(v, o, WAVE);
             if (l >= o) v = fmaxf(v, u);
         }
         if (l == WAVE - 1) wmax[w] = v;
@@ -215,6 +224,45 @@ __global__ __launch_bounds__(1024) void knn_pmax(const float* __restrict__ norms
         if (t == 1023) carry_s = v;
         __syncthreads();
     }
+    if (t == 0) blk[blockIdx.x] = carry_s;
+}
+
+__global__ __launch_bounds__(1024) void knn_pmax_carry(float* __restrict__ blk, int64_t nb,
+                                                       const float* __restrict__ pmax, int64_t r0) {
+    __shared__ float wmax[16];
+    __shared__ float carry_s;
+    const int t = threadIdx.x, l = t & 63, w = t >> 6;
+    if (t == 0) carry_s = r0 > 0 ? pmax[r0 - 1] : 0.0f;
+    __syncthreads();
+    for (int64_t base = 0; base < nb; base += 1024) {
+        const int64_t b = base + t;
+        const float x = b < nb ? blk[b] : 0.0f;
+        float v = x;
+#pragma unroll
+        for (int o = 1; o < WAVE; o <<= 1) {
+            const float u = __shfl_up(v, o, WAVE);
+            if (l >= o) v = fmaxf(v, u);
+        }
+        if (l == WAVE - 1) wmax[w] = v;
+        __syncthreads();
+        float pre = carry_s;
+        for (int j = 0; j < w; ++j) pre = fmaxf(pre, wmax[j]);
+        // exclusive: the carry before this chunk is the inclusive prefix of
+        // the chunks before it
+        const float up = __shfl_up(v, 1, WAVE);
+        const float excl = l > 0 ? fmaxf(pre, up) : pre;
+        v = fmaxf(v, pre);
+        __syncthreads();
+        if (b < nb) blk[b] = excl;
+        if (t == 1023) carry_s = v;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void knn_pmax_apply(float* __restrict__ pmax, int64_t r0, int64_t r1,
+                                                      const float* __restrict__ blk) {
+    const int64_t i = r0 + (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < r1) pmax[i] = fmaxf(pmax[i], blk[(i - r0) / PMAX_CHUNK]);
 }
 
 // Rigorous bound on |d'_qj + n_q - ||x_q - x_j||^2| for the FP32 contraction:
@@ -596,6 +644,7 @@ struct TileArgs {
     int kc;
     const float* tau0;
     int64_t tau0_stride;
+    const float* tau_seed;
     const int32_t* death;
     const int32_t* views;
     int32_t view;
@@ -757,7 +806,9 @@ __global__ __launch_bounds__((TileGeom<P, SMALL>::THREADS)) __attribute__((amdgp
         sq_e8 = (P == ATSNE_PREC_FP8_E4M3 && qvalid) ? e8m0_of(a.scales[self]) : 127;
         tau = -INFINITY;
         if (qvalid && key_visible(death, self, a.views ? a.views[mq] : a.view)) {
-            tau = INFINITY;
+            // keys with d' <= the seed pass; nextafter keeps the seed's own
+            // value, as the filter below is strict
+            tau = a.tau_seed ? nextafterf(a.tau_seed[self], INFINITY) : INFINITY;
             if (a.tau0) {
                 // reverse mode: only keys that may beat the row's farthest
                 // neighbour; d' = d - n_q, widened by the contraction bound
@@ -1344,6 +1395,8 @@ struct SelArgs {
     int64_t out_stride;
     int32_t* scan_list;
     int32_t* scan_count;
+    float* tau_out;  // threshold mode (seeding pass): see Batch
+    const int32_t* tau_map;
 };
 
 // Gathers the union of a row's candidate slots; returns the threshold key
@@ -1431,6 +1484,19 @@ __global__ __launch_bounds__(64 * SEL_ROWS) void knn_select(SelArgs a, int kcap)
         wave_sync();
         return ks;
     };
+    if (a.tau_out) {
+        // threshold mode: the kc-th smallest key of the row's union
+        const uint64_t ks = union_threshold(
+            [&](auto f) {
+                for (int s = 0; s < a.S; ++s) {
+                    const uint64_t* sl = base + (size_t)s * a.cap;
+                    for (int i = l; i < cnt[s]; i += WAVE) f(sl[i]);
+                }
+            },
+            min(kc, total), total, hist);
+        if (l == 0) a.tau_out[a.tau_map ? (int64_t)a.tau_map[q] : q] = total >= kc ? key_dist(ks) : INFINITY;
+        return;
+    }
     uint64_t kstar;
     if (!a.death && total <= SEL_RK * WAVE) {
         // small unions are read once into registers, every load in flight
@@ -1843,6 +1909,7 @@ size_t corpus_bytes(int prec, int64_t rows_cap, int32_t D) {
     a.take<float>(rows);
     a.take<float>(rows);
     a.take<float>(rows);
+    a.take<float>(rows / PMAX_CHUNK + 1);  // chunk carries of the norms' prefix max
     return a.used;
 }
 
@@ -1861,6 +1928,7 @@ void corpus_bind(Corpus& c, int prec, const float* X, int64_t ld, int32_t D, int
     c.norms = a.take<float>(c.rows_cap);
     c.scales = a.take<float>(c.rows_cap);
     c.pmax = a.take<float>(c.rows_cap);
+    c.pmax_blk = a.take<float>(c.rows_cap / PMAX_CHUNK + 1);
 }
 
 atsne_status corpus_prep(const Corpus& c, int64_t r0, int64_t r1, int64_t n_live, hipStream_t st) {
@@ -1885,7 +1953,12 @@ atsne_status corpus_prep(const Corpus& c, int64_t r0, int64_t r1, int64_t n_live
                                                                   c.norms, c.scales);
     }
     ATSNE_LAUNCH_CHECK();
-    knn_pmax<<<dim3(1), dim3(1024), 0, st>>>(c.norms, c.pmax, r0, r1);
+    const int64_t nb = ceil_div(r1 - r0, (int64_t)PMAX_CHUNK);
+    knn_pmax_local<<<dim3((unsigned)nb), dim3(1024), 0, st>>>(c.norms, c.pmax, r0, r1, c.pmax_blk);
+    ATSNE_LAUNCH_CHECK();
+    knn_pmax_carry<<<dim3(1), dim3(1024), 0, st>>>(c.pmax_blk, nb, c.pmax, r0);
+    ATSNE_LAUNCH_CHECK();
+    knn_pmax_apply<<<dim3((unsigned)ceil_div(r1 - r0, (int64_t)256)), dim3(256), 0, st>>>(c.pmax, r0, r1, c.pmax_blk);
     ATSNE_LAUNCH_CHECK();
     return ATSNE_OK;
 }
@@ -2029,6 +2102,7 @@ static atsne_status launch_tile(const Corpus& c, const Batch& b, const SearchPla
     t.kc = b.kc;
     t.tau0 = b.tau0;
     t.tau0_stride = b.tau0_stride;
+    t.tau_seed = b.tau_seed;
     t.death = c.death;
     t.views = b.views;
     t.view = b.view;
@@ -2039,6 +2113,9 @@ static atsne_status launch_tile(const Corpus& c, const Batch& b, const SearchPla
     t.tile_hi = p.tile_hi;
     t.cap = p.cap;
     t.final_keep = (!b.blk_q && !b.tau0 && p.tiles_per_split == 1) ? p.kt : 0;
+    // threshold mode: the select cuts each row's union (held in registers
+    // while it fits) instead of a serial exact shrink per query in the tile
+    if (b.tau_out) t.final_keep = SEL_RK * WAVE / std::max(1, p.S);
     t.blk_q = b.blk_q;
     t.blk_t = b.blk_t;
     t.tl_idx = b.tl_idx;
@@ -2067,7 +2144,8 @@ static atsne_status launch_tile(const Corpus& c, const Batch& b, const SearchPla
         }
     }
     if (!t.segs && p.stream_wgs) t.tiles_per_split = (int)ceil_div(p.tile_hi - p.tile_lo, p.S);
-    ProfScope ps_(b.tau0 ? "knn_tile_reverse" : (b.blk_q ? "knn_tile_list" : "knn_tile"), st);
+    ProfScope ps_(b.tau_out ? "seed_tile" : (b.tau0 ? "knn_tile_reverse" : (b.blk_q ? "knn_tile_list" : "knn_tile")),
+                  st);
     const dim3 grid(n_wg);
     if (p.small) {
         ATSNE_REQUIRE(!c.death && !b.blk_q && !b.tau0 && P != ATSNE_PREC_FP8_E4M3, ATSNE_E_UNSUPPORTED,
@@ -2086,8 +2164,16 @@ static atsne_status launch_tile(const Corpus& c, const Batch& b, const SearchPla
         else
             knn_tile<P, TILE_PLAIN, false><<<grid, block, 0, st>>>(t);
     } else {
-        ATSNE_REQUIRE(!c.death && !b.blk_q, ATSNE_E_UNSUPPORTED,
-                      "deletion stamps and tile lists need an exact contraction's corpus");
+        ATSNE_REQUIRE(!c.death && (!b.blk_q || P == ATSNE_PREC_FP8_E4M3), ATSNE_E_UNSUPPORTED,
+                      "deletion stamps need an exact contraction's corpus, tile lists an exact or the FP8 one");
+        if constexpr (P == ATSNE_PREC_FP8_E4M3) {
+            if (b.blk_q) {
+                // the seeding pass of a large FP8 search
+                knn_tile<P, TILE_LIST, false><<<grid, dim3(TileGeom<P>::THREADS), 0, st>>>(t);
+                ATSNE_LAUNCH_CHECK();
+                return ATSNE_OK;
+            }
+        }
         knn_tile<P, TILE_PLAIN, false><<<grid, dim3(TileGeom<P>::THREADS), 0, st>>>(t);
     }
     ATSNE_LAUNCH_CHECK();
@@ -2136,6 +2222,8 @@ static SelArgs sel_args(const Corpus& c, const Batch& b, const SearchPlan& p, co
     s.tl_idx = b.tl_idx;
     s.slots = w.slots;
     s.counts = w.counts;
+    s.tau_out = b.tau_out;
+    s.tau_map = b.tau_map;
     s.out_idx = b.out_idx;
     s.out_d2 = b.out_d2;
     s.out_d2_lo = b.out_d2_lo;
@@ -2154,7 +2242,7 @@ atsne_status knn_search(const Corpus& c, const Batch& b, const SearchPlan& p, vo
     ATSNE_TRY(launch_tile_any(c, b, p, w, st));
     const SelArgs s = sel_args(c, b, p, w);
     {
-        ProfScope ps_("knn_select", st);
+        ProfScope ps_(b.tau_out ? "seed_select" : "knn_select", st);
         const int kcap = p.kc_max;
         const int rows = sel_rows(kcap);
         const size_t lds = rows * select_lds_bytes(kcap);
@@ -2208,6 +2296,8 @@ atsne_status knn_reverse(const Corpus& c, const Batch& b, const SearchPlan& p, i
 }
 
 // ---- C ABI: standalone search over a caller corpus ----
+constexpr int64_t KNN_SEED_MIN_N = (int64_t)1 << 18;  // full FP8 searches from this many rows are seeded
+
 struct KnnPlan {
     int prec, k, kc;
     int64_t N, M, Mb;
@@ -2270,6 +2360,26 @@ static atsne_status knn_impl(const float* X, int64_t N, int32_t D, int64_t ld, c
     ATSNE_TRY(make_plan(N, M, D, (int)prec, k, k_cand, p));
     if (M == 0) return ATSNE_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
+    // A full FP8 search over many rows first bounds each row's k'-th key
+    // code from the keys near it (fp8_seed_thresholds), so its tiles append
+    // about k' keys per row instead of every key below a threshold that
+    // tightens only as the corpus streams past; the outputs are unchanged.
+    // ATSNE_FP8_SEED=0 turns the pass off.
+    float* tau_seed = nullptr;
+    std::unique_ptr<float, void (*)(float*)> tau_guard(nullptr, [](float* q) { (void)hipFree(q); });
+    if (prec == ATSNE_PREC_FP8_E4M3 && !qids && N >= KNN_SEED_MIN_N && ld == D) {
+        const char* env = std::getenv("ATSNE_FP8_SEED");
+        if (!(env && env[0] == '0')) {
+            if (hipMalloc((void**)&tau_seed, sizeof(float) * N) != hipSuccess) {
+                set_error("device allocation of %lld seed thresholds failed", (long long)N);
+                return ATSNE_E_NOMEM;
+            }
+            tau_guard.reset(tau_seed);
+            ProfScope ps_("seed_total", st);
+            ProfQuiet quiet_;  // the pass's own searches report as seed_total only
+            ATSNE_TRY(fp8_seed_thresholds(X, N, D, ld, p.kc, tau_seed, st));
+        }
+    }
     Scratch scr;
     ATSNE_TRY(scr.acquire(ws, ws_bytes, p.total, st));
     Corpus c;
@@ -2290,8 +2400,11 @@ static atsne_status knn_impl(const float* X, int64_t N, int32_t D, int64_t ld, c
         b.out_d2_lo = nbr_d2_lo ? nbr_d2_lo + m0 * k : nullptr;
         b.out_flags = flags ? flags + m0 : nullptr;
         b.out_stride = k;
+        b.tau_seed = tau_seed;
         ATSNE_TRY(knn_search(c, b, p.sp, sws, st));
     }
+    // the thresholds are freed on return: the searches reading them first
+    if (tau_seed) ATSNE_HIP(hipStreamSynchronize(st));
     return ATSNE_OK;
 }
 

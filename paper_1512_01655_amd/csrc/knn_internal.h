@@ -23,6 +23,7 @@ struct Corpus {
     float* norms = nullptr;
     float* scales = nullptr;
     float* pmax = nullptr;
+    float* pmax_blk = nullptr;  // chunk carries of the prefix max (scratch of corpus_prep)
     // Optional per-row deletion stamps (serving): row j is visible to a
     // request whose view is v iff death[j] >= v (INT32_MAX = never deleted).
     const int32_t* death = nullptr;
@@ -52,10 +53,21 @@ struct Batch {
     int64_t tau0_stride = 0;      // element stride of tau0 (rows' d_max inside a neighbour table)
     const int32_t* views = nullptr;  // per-row view for deletion visibility; null: view
     int32_t view = 0;
-    // Tile lists (restricted search, FP32): block b holds batch rows
+    // Seeded threshold (plain search): tau_seed[q] (indexed by corpus id) is
+    // at least the k'-th smallest key code d' of row q over all keys, so the
+    // tile keeps only keys with d' <= tau_seed[q] from the start; the
+    // candidates, and so every output, are those of the unseeded search.
+    const float* tau_seed = nullptr;
+    // Threshold mode (seeding pass): the select writes, for batch row m with
+    // corpus id q, the k'-th smallest d' of its candidates (+inf with fewer)
+    // to tau_out[tau_map ? tau_map[q] : q] and writes no neighbour lists.
+    float* tau_out = nullptr;
+    const int32_t* tau_map = nullptr;
+    // Tile lists (restricted search, FP32, FP32X3, FP8): block b holds batch rows
     // [blk_q[b], blk_q[b+1]) (at most KNN_KT of them) and searches the key
-    // tiles tl_idx[blk_t[b] .. blk_t[b+1]) (ascending); row_blk[m] is the
-    // block of row m.  Null blk_q: every row searches [key_lo, nlim).
+    // tiles tl_idx[blk_t[b] .. blk_t[b+1]) (distinct; ascending where the
+    // exact scan may walk them, any order in threshold mode); row_blk[m] is
+    // the block of row m.  Null blk_q: every row searches [key_lo, nlim).
     int64_t n_blocks = 0;
     const int32_t* blk_q = nullptr;
     const int32_t* blk_t = nullptr;
@@ -122,6 +134,13 @@ atsne_status sort_pairs_u64(void* tmp, size_t tmp_bytes, const uint64_t* kin, co
 // Plan a search restricted to per-block tile lists (Batch::blk_q set):
 // M rows in n_blocks blocks, S splits per block.
 SearchPlan plan_list_search(int64_t M, int64_t n_blocks, int k_max, int kc_max, int S);
+
+// Seeding pass of a large FP8 search (the k-means partition of the
+// approximate search; each point's own cluster and its nearest clusters,
+// searched in FP8 with the same tile kernel): tau[i] = the kc-th smallest
+// key code d' of point i over those keys, an upper bound of its kc-th
+// smallest over all keys.  tau is device [N]; the pass allocates its index.
+atsne_status fp8_seed_thresholds(const float* X, int64_t N, int32_t D, int64_t ld, int kc, float* tau, hipStream_t st);
 
 // Serving-loop data manipulation (Sec. 5.3); resident lists have k entries
 // per row, present entries first, absent ones (index -1, +inf) last.

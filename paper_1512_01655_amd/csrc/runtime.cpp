@@ -59,9 +59,14 @@ struct ProfRec {
 std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::vector<ProfRec> g_prof;
+thread_local int g_prof_quiet = 0;
 }  // namespace
 
+ProfQuiet::ProfQuiet() { ++g_prof_quiet; }
+ProfQuiet::~ProfQuiet() { --g_prof_quiet; }
+
 ProfScope::ProfScope(const char* name, hipStream_t s) : stream(s) {
+    if (g_prof_quiet > 0) return;
     std::lock_guard<std::mutex> lk(g_prof_mu);
     if (!g_prof_on) return;
     ProfRec r;

@@ -226,6 +226,17 @@ def test_knn_subset_empty(A, prec):
     assert idx.shape == (0, 10) and d2.shape == (0, 10) and fl.shape == (0,)
 
 
+def test_knn_fp8_seeded_equals_unseeded(A, monkeypatch):
+    # a full FP8 search of at least 2^18 rows first bounds each row's k'-th
+    # key code from the keys near it; rows, distances and flags are those of
+    # the search without that pass, bit for bit
+    X = datagen.mixture_anisotropic(n=300000)
+    a = run_knn(A, X, 150, "fp8", 300)
+    monkeypatch.setenv("ATSNE_FP8_SEED", "0")
+    b = run_knn(A, X, 150, "fp8", 300)
+    assert all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
 def test_knn_errors(A):
     import torch
 
