@@ -630,7 +630,7 @@ static std::vector<std::vector<int32_t>> seed_tiles(const atsne_ivf& ix, int n_p
 }
 
 atsne_status fp8_seed_thresholds(const float* X, int64_t N, int32_t D, int64_t ld, int kc, float* tau,
-                                 hipStream_t st) {
+                                 int32_t* order, hipStream_t st) {
     ATSNE_REQUIRE(ld == D, ATSNE_E_UNSUPPORTED, "seeding needs contiguous rows");
     const int C = (int)std::min<int64_t>(IVF_MAX_C, std::max<int64_t>(2, N / SEED_CLUSTER_ROWS));
     std::vector<int32_t> init(C);
@@ -639,6 +639,7 @@ atsne_status fp8_seed_thresholds(const float* X, int64_t N, int32_t D, int64_t l
     ATSNE_TRY(atsne_ivf_build(X, N, D, C, init.data(), 0, &ixp, st));
     std::unique_ptr<atsne_ivf, atsne_status (*)(atsne_ivf*)> guard(ixp, atsne_ivf_destroy);
     atsne_ivf& ix = *ixp;
+    if (order) ATSNE_HIP(hipMemcpyAsync(order, ix.perm, sizeof(int32_t) * N, hipMemcpyDeviceToDevice, st));
     // FP8 copy of the sorted corpus (per-row scales: the rows' FP8 codes,
     // norms and scales equal those of the same rows in the caller's order)
     const int64_t cap = ceil_div(N, (int64_t)KNN_KT) * KNN_KT;

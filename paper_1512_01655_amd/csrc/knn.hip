@@ -1397,6 +1397,7 @@ struct SelArgs {
     int32_t* scan_count;
     float* tau_out;  // threshold mode (seeding pass): see Batch
     const int32_t* tau_map;
+    const int32_t* sel_order;  // see Batch
 };
 
 // Gathers the union of a row's candidate slots; returns the threshold key
@@ -1443,8 +1444,9 @@ __global__ __launch_bounds__(64 * SEL_ROWS) void knn_select(SelArgs a, int kcap)
     float* sorted_lo = cdl + kcap;
     int32_t& ncand = *reinterpret_cast<int32_t*>(sorted_lo + kcap);
     const int l = lane_id();
-    const int64_t m = (int64_t)blockIdx.x * (blockDim.x >> 6) + w;
-    if (m >= a.M) return;  // waves are independent: no workgroup barrier below
+    const int64_t m_lin = (int64_t)blockIdx.x * (blockDim.x >> 6) + w;
+    if (m_lin >= a.M) return;  // waves are independent: no workgroup barrier below
+    const int64_t m = a.sel_order ? (int64_t)a.sel_order[m_lin] : m_lin;
     const int64_t q = load_qid(a.qids, a.m0, m);
     const int64_t nl = a.nlims ? (int64_t)a.nlims[m] : a.nlim;
     const int k = a.ks ? a.ks[m] : a.k;
@@ -2224,6 +2226,7 @@ static SelArgs sel_args(const Corpus& c, const Batch& b, const SearchPlan& p, co
     s.counts = w.counts;
     s.tau_out = b.tau_out;
     s.tau_map = b.tau_map;
+    s.sel_order = b.sel_order;
     s.out_idx = b.out_idx;
     s.out_d2 = b.out_d2;
     s.out_d2_lo = b.out_d2_lo;
@@ -2366,7 +2369,9 @@ static atsne_status knn_impl(const float* X, int64_t N, int32_t D, int64_t ld, c
     // tightens only as the corpus streams past; the outputs are unchanged.
     // ATSNE_FP8_SEED=0 turns the pass off.
     float* tau_seed = nullptr;
+    int32_t* order = nullptr;  // the points in cluster order (the seeding pass's partition)
     std::unique_ptr<float, void (*)(float*)> tau_guard(nullptr, [](float* q) { (void)hipFree(q); });
+    std::unique_ptr<int32_t, void (*)(int32_t*)> order_guard(nullptr, [](int32_t* q) { (void)hipFree(q); });
     if (prec == ATSNE_PREC_FP8_E4M3 && !qids && N >= KNN_SEED_MIN_N && ld == D) {
         const char* env = std::getenv("ATSNE_FP8_SEED");
         if (!(env && env[0] == '0')) {
@@ -2375,9 +2380,14 @@ static atsne_status knn_impl(const float* X, int64_t N, int32_t D, int64_t ld, c
                 return ATSNE_E_NOMEM;
             }
             tau_guard.reset(tau_seed);
+            if (hipMalloc((void**)&order, sizeof(int32_t) * N) != hipSuccess) {
+                set_error("device allocation of the %lld-point cluster order failed", (long long)N);
+                return ATSNE_E_NOMEM;
+            }
+            order_guard.reset(order);
             ProfScope ps_("seed_total", st);
             ProfQuiet quiet_;  // the pass's own searches report as seed_total only
-            ATSNE_TRY(fp8_seed_thresholds(X, N, D, ld, p.kc, tau_seed, st));
+            ATSNE_TRY(fp8_seed_thresholds(X, N, D, ld, p.kc, tau_seed, order, st));
         }
     }
     Scratch scr;
@@ -2401,9 +2411,11 @@ static atsne_status knn_impl(const float* X, int64_t N, int32_t D, int64_t ld, c
         b.out_flags = flags ? flags + m0 : nullptr;
         b.out_stride = k;
         b.tau_seed = tau_seed;
+        // one batch of all rows: the select takes them in cluster order
+        if (order && b.M == N && m0 == 0) b.sel_order = order;
         ATSNE_TRY(knn_search(c, b, p.sp, sws, st));
     }
-    // the thresholds are freed on return: the searches reading them first
+    // the thresholds and the order are freed on return: the searches reading them first
     if (tau_seed) ATSNE_HIP(hipStreamSynchronize(st));
     return ATSNE_OK;
 }

@@ -63,6 +63,11 @@ struct Batch {
     // to tau_out[tau_map ? tau_map[q] : q] and writes no neighbour lists.
     float* tau_out = nullptr;
     const int32_t* tau_map = nullptr;
+    // Select order (full search in one batch): the select takes batch rows
+    // in the order sel_order[0..M) (a permutation of [0, M)), e.g. grouped
+    // by cluster so that consecutive rows gather overlapping candidate rows
+    // through the caches; outputs stay at their rows.
+    const int32_t* sel_order = nullptr;
     // Tile lists (restricted search, FP32, FP32X3, FP8): block b holds batch rows
     // [blk_q[b], blk_q[b+1]) (at most KNN_KT of them) and searches the key
     // tiles tl_idx[blk_t[b] .. blk_t[b+1]) (distinct; ascending where the
@@ -140,7 +145,9 @@ SearchPlan plan_list_search(int64_t M, int64_t n_blocks, int k_max, int kc_max, 
 // searched in FP8 with the same tile kernel): tau[i] = the kc-th smallest
 // key code d' of point i over those keys, an upper bound of its kc-th
 // smallest over all keys.  tau is device [N]; the pass allocates its index.
-atsne_status fp8_seed_thresholds(const float* X, int64_t N, int32_t D, int64_t ld, int kc, float* tau, hipStream_t st);
+// order (device [N], may be null) receives the points in cluster order.
+atsne_status fp8_seed_thresholds(const float* X, int64_t N, int32_t D, int64_t ld, int kc, float* tau,
+                                 int32_t* order, hipStream_t st);
 
 // Serving-loop data manipulation (Sec. 5.3); resident lists have k entries
 // per row, present entries first, absent ones (index -1, +inf) last.

@@ -237,6 +237,19 @@ def test_knn_fp8_seeded_equals_unseeded(A, monkeypatch):
     assert all(np.array_equal(x, y) for x, y in zip(a, b))
 
 
+def test_knn_fp8_seeded_equals_unseeded_with_ties(A, monkeypatch):
+    # 2^18 rows drawn from 2000 prototypes: every row has ~130 exact
+    # duplicates, so many keys share the k'-th key code exactly; the seeded
+    # threshold keeps every key at or below it and the rows stay bit-identical
+    rng = np.random.default_rng(21)
+    proto = rng.normal(size=(2000, 64)).astype(np.float32)
+    X = proto[rng.integers(0, 2000, size=1 << 18)]
+    a = run_knn(A, X, 150, "fp8", 300)
+    monkeypatch.setenv("ATSNE_FP8_SEED", "0")
+    b = run_knn(A, X, 150, "fp8", 300)
+    assert all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
 def test_knn_errors(A):
     import torch
 
