@@ -846,10 +846,14 @@ __global__ __launch_bounds__((TileGeom<P, SMALL>::THREADS)) __attribute__((amdgp
         const uint4* qa1 = qb + (uint64_t)qr1 * (uint64_t)row_units;
         const uint4* qa2 = qb + (uint64_t)qr2 * (uint64_t)row_units;
         const uint4* qa3 = qb + (uint64_t)qr3 * (uint64_t)row_units;
-        lds_dma16(qa0, qs + 64 * w);
-        lds_dma16(qa1, qs + 64 * (w + TILE_WAVES));
-        lds_dma16(qa2, qs + 64 * (w + 2 * TILE_WAVES));
-        lds_dma16(qa3, qs + 64 * (w + 3 * TILE_WAVES));
+        // single-chunk rows: the query chunk is the same for every tile of a
+        // segment, so only its first two tiles (one per buffer) load it
+        if (n_chunks > 1 || pos < tile_begin + 2) {
+            lds_dma16(qa0, qs + 64 * w);
+            lds_dma16(qa1, qs + 64 * (w + TILE_WAVES));
+            lds_dma16(qa2, qs + 64 * (w + 2 * TILE_WAVES));
+            lds_dma16(qa3, qs + 64 * (w + 3 * TILE_WAVES));
+        }
 #pragma unroll
         for (int j = 0; j < KT / RSTEP; ++j) lds_dma16(kb + j * kstep_, ks + 64 * (w + TILE_WAVES * j));
         if (c == 0 && w < KT / 64) {
