@@ -2379,19 +2379,29 @@ static atsne_status knn_impl(const float* X, int64_t N, int32_t D, int64_t ld, c
     if (prec == ATSNE_PREC_FP8_E4M3 && !qids && N >= KNN_SEED_MIN_N && ld == D) {
         const char* env = std::getenv("ATSNE_FP8_SEED");
         if (!(env && env[0] == '0')) {
-            if (hipMalloc((void**)&tau_seed, sizeof(float) * N) != hipSuccess) {
-                set_error("device allocation of %lld seed thresholds failed", (long long)N);
-                return ATSNE_E_NOMEM;
+            // the pass is an optimisation: without the memory for it the
+            // search runs unseeded (same results)
+            atsne_status s = ATSNE_E_NOMEM;
+            if (hipMalloc((void**)&tau_seed, sizeof(float) * N) == hipSuccess) {
+                tau_guard.reset(tau_seed);
+                if (hipMalloc((void**)&order, sizeof(int32_t) * N) == hipSuccess) {
+                    order_guard.reset(order);
+                    ProfScope ps_("seed_total", st);
+                    ProfQuiet quiet_;  // the pass's own searches report as seed_total only
+                    s = fp8_seed_thresholds(X, N, D, ld, p.kc, tau_seed, order, st);
+                }
             }
-            tau_guard.reset(tau_seed);
-            if (hipMalloc((void**)&order, sizeof(int32_t) * N) != hipSuccess) {
-                set_error("device allocation of the %lld-point cluster order failed", (long long)N);
-                return ATSNE_E_NOMEM;
+            if (s == ATSNE_E_NOMEM) {
+                (void)hipGetLastError();  // clear a failed allocation's sticky error
+                (void)hipStreamSynchronize(st);
+                tau_guard.reset();
+                order_guard.reset();
+                tau_seed = nullptr;
+                order = nullptr;
+                clear_error();
+            } else if (s != ATSNE_OK) {
+                return s;
             }
-            order_guard.reset(order);
-            ProfScope ps_("seed_total", st);
-            ProfQuiet quiet_;  // the pass's own searches report as seed_total only
-            ATSNE_TRY(fp8_seed_thresholds(X, N, D, ld, p.kc, tau_seed, order, st));
         }
     }
     Scratch scr;
