@@ -388,9 +388,12 @@ static atsne_status sym_run(const SymPlan& p, RowsIn rin, const int32_t* in_col,
     sym_block_scan<<<dim3((unsigned)nb), dim3(1024), 0, st>>>(cnt, N, boff, row_ptr);
     ATSNE_LAUNCH_CHECK();
     const float inv = (float)(1.0 / (2.0 * (double)N));
+    // k <= 128: mirrored runs average k entries, so a 256-entry LDS cache
+    // covers nearly every row and the smaller footprint keeps more waves per
+    // CU (0.55 -> 0.52 ms at N = 70000 against a 1024-entry cache)
     if (rin.ptr == nullptr && rin.k <= 128)
-        sym_row_emit<128, 1024><<<rows4, blk, 0, st>>>(rin, in_col, in_val, N, k1, v1, runs, row_ptr, inv, 2 * E, col,
-                                                        val);
+        sym_row_emit<128, 256><<<rows4, blk, 0, st>>>(rin, in_col, in_val, N, k1, v1, runs, row_ptr, inv, 2 * E, col,
+                                                       val);
     else if (rin.ptr == nullptr && rin.k <= 256)
         sym_row_emit<256, 1024><<<rows4, blk, 0, st>>>(rin, in_col, in_val, N, k1, v1, runs, row_ptr, inv, 2 * E, col,
                                                         val);
