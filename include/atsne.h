@@ -126,9 +126,11 @@ atsne_status atsne_knn_workspace_size(int64_t N, int64_t M, int32_t D, atsne_pre
  *   key below a threshold that tightens as the corpus streams past.  The
  *   outputs are those of the unseeded search bit for bit.  The pass
  *   allocates its own device memory (about 9 GB at its peak for N = 10^6,
- *   freed before the search) whatever ws is, and without that memory the
- *   search runs unseeded; ATSNE_FP8_SEED=0 in the environment turns it
- *   off.
+ *   freed before the search) whatever ws is.  Without that memory, for D
+ *   above 4096, or when the cells would cover more than a tenth of all row
+ *   pairs, the search runs unseeded; ATSNE_FP8_SEED=0 in the environment
+ *   turns the pass off.  With kernel timing on, the pass is one "seed_total"
+ *   record, plus an empty "seed_declined" record when it stepped aside.
  */
 atsne_status atsne_knn(const float* X, int64_t N, int32_t D, int64_t ld, atsne_precision prec, int32_t k,
                        int32_t k_cand, int32_t* nbr_idx, float* nbr_d2, float* nbr_d2_lo, uint8_t* flags, void* ws,

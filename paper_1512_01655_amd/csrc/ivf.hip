@@ -649,6 +649,13 @@ atsne_status fp8_seed_thresholds(const float* X, int64_t N, int32_t D, int64_t l
     corpus_bind(c8, ATSNE_PREC_FP8_E4M3, ix.Xperm, D, D, cap, cm.p);
     ATSNE_TRY(corpus_prep(c8, 0, cap, N, st));
     const auto tiles = seed_tiles(ix, SEED_PROBE, kc);
+    // decline when the cells are too coarse to pay (e.g. data in one cell):
+    // the lists would cover more than a tenth of all row pairs
+    double pairs = 0;
+    for (int c = 0; c < C; ++c)
+        pairs += (double)(ix.start[c + 1] - ix.start[c]) * (double)tiles[c].size() * IVF_TILE;
+    ATSNE_REQUIRE(pairs <= 0.1 * (double)N * (double)N, ATSNE_E_UNSUPPORTED,
+                  "seeding lists would cover %.0f%% of the row pairs", 100.0 * pairs / ((double)N * (double)N));
     for (int c0 = 0; c0 < C;) {
         int c1 = c0 + 1;
         while (c1 < C && ix.start[c1 + 1] - ix.start[c0] <= SEED_BATCH_ROWS) ++c1;

@@ -2379,8 +2379,9 @@ static atsne_status knn_impl(const float* X, int64_t N, int32_t D, int64_t ld, c
     if (prec == ATSNE_PREC_FP8_E4M3 && !qids && N >= KNN_SEED_MIN_N && ld == D) {
         const char* env = std::getenv("ATSNE_FP8_SEED");
         if (!(env && env[0] == '0')) {
-            // the pass is an optimisation: without the memory for it the
-            // search runs unseeded (same results)
+            // the pass is an optimisation: without the memory for it, or
+            // where it does not apply (D above the partition's limit, cells
+            // too coarse to pay), the search runs unseeded (same results)
             atsne_status s = ATSNE_E_NOMEM;
             if (hipMalloc((void**)&tau_seed, sizeof(float) * N) == hipSuccess) {
                 tau_guard.reset(tau_seed);
@@ -2391,8 +2392,11 @@ static atsne_status knn_impl(const float* X, int64_t N, int32_t D, int64_t ld, c
                     s = fp8_seed_thresholds(X, N, D, ld, p.kc, tau_seed, order, st);
                 }
             }
-            if (s == ATSNE_E_NOMEM) {
+            if (s == ATSNE_E_NOMEM || s == ATSNE_E_UNSUPPORTED) {
                 (void)hipGetLastError();  // clear a failed allocation's sticky error
+                // a pass that ran but stepped aside shows in the kernel
+                // timing as an empty "seed_declined" record
+                if (order) ProfScope declined_("seed_declined", st);
                 (void)hipStreamSynchronize(st);
                 tau_guard.reset();
                 order_guard.reset();
