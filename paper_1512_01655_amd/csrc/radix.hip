@@ -12,7 +12,9 @@
 //                 and the digit's total; radix_scan_t then scans the totals
 //   radix_move    stable scatter: each tile, chunk by chunk (4096 keys held
 //                 in registers, 16 per thread), ranks its keys by wave
-//                 multi-split and places them after the keys of smaller
+//                 multi-split, stages the chunk in LDS in (digit, input)
+//                 order and writes it out so that consecutive lanes store
+//                 consecutive positions of a digit, after the keys of smaller
 //                 digits, of earlier tiles and of earlier keys of the tile
 // Keys are moved, never compared, so the sort is exact and deterministic.
 #include <algorithm>
@@ -105,7 +107,11 @@ __global__ __launch_bounds__(256) void radix_move(const uint64_t* __restrict__ k
                                                   int shift, int bits, const uint32_t* __restrict__ cnt,
                                                   const uint32_t* __restrict__ doff) {
     __shared__ uint32_t start[RADIX_MAX_BINS];    // tile's next output position of each digit
-    __shared__ uint32_t wcnt[4][RADIX_MAX_BINS];  // per wave: its count of each digit, then its offset within the chunk
+    __shared__ uint32_t wcnt[4][RADIX_MAX_BINS];  // per wave: its count of each digit, then its offset within the digit
+    __shared__ uint32_t cofs[RADIX_MAX_BINS];     // per digit: its count in the chunk, then its first staged slot
+    __shared__ uint32_t wsum[4];
+    __shared__ uint64_t sk[RADIX_CHUNK];          // the chunk's keys staged in (digit, input) order
+    __shared__ uint32_t sv[RADIX_CHUNK];
     const int t = threadIdx.x, l = t & 63, w = t >> 6;
     const int bins = 1 << bits;
     for (int b = t; b < bins; b += 256) start[b] = doff[b] + cnt[(int64_t)b * g.n_tiles + blockIdx.x];
@@ -144,39 +150,68 @@ __global__ __launch_bounds__(256) void radix_move(const uint64_t* __restrict__ k
             wave_sync();
         }
         __syncthreads();
-        // per digit: the waves' offsets within the chunk, and the chunk's total
-        uint32_t tot[RADIX_MAX_BINS / 256];
-#pragma unroll
-        for (int q = 0; q < RADIX_MAX_BINS / 256; ++q) {
-            const int b = t + 256 * q;
+        // per digit: the waves' offsets within the digit, and its chunk count
+        for (int b = t; b < bins; b += 256) {
             uint32_t a = 0;
-            if (b < bins) {
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const uint32_t x = wcnt[u][b];
-                    wcnt[u][b] = a;
-                    a += x;
-                }
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t x = wcnt[u][b];
+                wcnt[u][b] = a;
+                a += x;
             }
-            tot[q] = a;
+            cofs[b] = a;
         }
         __syncthreads();
+        // exclusive scan of the chunk counts over the digits (thread t holds
+        // digits 4t .. 4t + 3): each digit's first slot in the staged chunk
+        uint32_t c4[4], s = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int b = 4 * t + u;
+            c4[u] = b < bins ? cofs[b] : 0u;
+            s += c4[u];
+        }
+        const uint32_t incl = wave_incl_scan(s);
+        if (l == 63) wsum[w] = incl;
+        __syncthreads();
+        uint32_t run = incl - s;
+        for (int i = 0; i < w; ++i) run += wsum[i];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int b = 4 * t + u;
+            if (b < bins) cofs[b] = run;
+            run += c4[u];
+        }
+        __syncthreads();
+        // stage the chunk in (digit, input) order: slot = the key's stable
+        // rank in the chunk, below the chunk's key count
 #pragma unroll
         for (int r = 0; r < RADIX_PER_THREAD; ++r) {
             if (wb + 64 * r + l < e1) {
                 const uint32_t d = radix_digit(k[r], shift, bits);
-                const uint32_t p = start[d] + wcnt[w][d] + pos[r];
-                if (p < (uint64_t)g.n) {  // always true: the guard keeps every store in bounds
-                    kout[p] = k[r];
-                    if (vout) vout[p] = v[r];
-                }
+                const uint32_t q = cofs[d] + wcnt[w][d] + pos[r];
+                sk[q] = k[r];
+                if (vin) sv[q] = v[r];
+            }
+        }
+        __syncthreads();
+        // write the staged chunk out: consecutive slots of a digit go to
+        // consecutive positions, after the digit's keys of earlier chunks
+        const int n_c = (int)std::min<int64_t>(RADIX_CHUNK, e1 - c0);
+        for (int q = t; q < n_c; q += 256) {
+            const uint64_t key = sk[q];
+            const uint32_t d = radix_digit(key, shift, bits);
+            const uint32_t p = start[d] + (uint32_t)q - cofs[d];
+            if (p < (uint64_t)g.n) {  // always true: the guard keeps every store in bounds
+                kout[p] = key;
+                if (vout) vout[p] = sv[q];
             }
         }
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < RADIX_MAX_BINS / 256; ++q) {
-            const int b = t + 256 * q;
-            if (b < bins) start[b] += tot[q];
+        for (int u = 0; u < 4; ++u) {
+            const int b = 4 * t + u;
+            if (b < bins) start[b] += c4[u];
         }
         __syncthreads();
     }

@@ -47,15 +47,14 @@ struct RowsIn {
 
 __device__ __forceinline__ bool sym_valid(int32_t j, int64_t i, int64_t N) { return j >= 0 && j < N && j != i; }
 
-__global__ __launch_bounds__(64) void sym_zero(int32_t* __restrict__ a, int n) {
-    if ((int)threadIdx.x < n) a[threadIdx.x] = 0;
-}
-
-// One wave per input row: the transposed keys of its entries.
+// One wave per input row: the transposed keys of its entries.  The first
+// thread also clears the error flag (fin[1]) that sym_row_count raises.
 __global__ __launch_bounds__(256) void sym_pack(RowsIn rin, const int32_t* __restrict__ col,
                                                 const float* __restrict__ val, int64_t N,
-                                                uint64_t* __restrict__ key, uint32_t* __restrict__ pv) {
+                                                uint64_t* __restrict__ key, uint32_t* __restrict__ pv,
+                                                int64_t* __restrict__ fin) {
     const int l = lane_id();
+    if (blockIdx.x == 0 && threadIdx.x == 0) fin[1] = 0;
     const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= N) return;
     const int64_t b = rin.begin(i), e = rin.end(i);
@@ -188,8 +187,11 @@ __global__ __launch_bounds__(1024) void sym_scan_small(const int64_t* __restrict
     if (t == 1023) out[n] = run;
 }
 
+// The total also goes to fin[0], which the host reads back with the error
+// flag in one copy.
 __global__ __launch_bounds__(1024) void sym_block_scan(const int64_t* __restrict__ c, int64_t n,
-                                                       const int64_t* __restrict__ boff, int64_t* __restrict__ out) {
+                                                       const int64_t* __restrict__ boff, int64_t* __restrict__ out,
+                                                       int64_t* __restrict__ fin) {
     __shared__ int64_t wsum[16];
     const int t = threadIdx.x, l = t & 63, w = t >> 6;
     const int64_t base = (int64_t)blockIdx.x * SYM_SCAN_BLOCK + 4 * t;
@@ -214,11 +216,16 @@ __global__ __launch_bounds__(1024) void sym_block_scan(const int64_t* __restrict
         if (base + q < n) out[base + q] = run;
         run += v[q];
     }
-    if (base < n && base + 4 >= n) out[n] = run;  // the thread holding the last count writes the total
+    if (base < n && base + 4 >= n) {  // the thread holding the last count writes the total
+        out[n] = run;
+        fin[0] = run;
+    }
 }
 
 // One wave per row, four rows per workgroup; a row holds at most CAP own
-// entries (its LDS) and its mirrored run is cached in LDS up to RUN entries.
+// entries (its LDS) and its mirrored run (columns and values) is cached in
+// LDS up to RUN entries, so that past the first loads the row's work reads
+// LDS only.
 template <int CAP, int RUN>
 __global__ __launch_bounds__(256) void sym_row_emit(RowsIn rin, const int32_t* __restrict__ col,
                                                     const float* __restrict__ val, int64_t N,
@@ -234,6 +241,7 @@ __global__ __launch_bounds__(256) void sym_row_emit(RowsIn rin, const int32_t* _
         int32_t scol[CAP];      // own columns in ascending order
         int32_t mpref[CAP + 1]; // flags of columns in both by rank, then their exclusive prefix
         int32_t cache[RUN];     // the mirrored run's columns
+        float cval[RUN];        // and values
     };
     __shared__ RowLds lds_all[4];
     const int l = lane_id();
@@ -243,12 +251,17 @@ __global__ __launch_bounds__(256) void sym_row_emit(RowsIn rin, const int32_t* _
     if (i >= N) return;  // waves are independent: no workgroup barrier below
     const int64_t b = rin.begin(i), e = rin.end(i);
     if (e - b > CAP) return;  // refused by the count (error flag)
+    const int64_t o = row_ptr[i];
     const int64_t m0 = run[i];
     const int n_in = (int)(run[i + 1] - m0);
     const uint64_t* mk = key + m0;
+    const uint32_t* mv = pv + m0;
     const bool in_lds = n_in <= RUN;
     if (in_lds)
-        for (int x = l; x < n_in; x += WAVE) L.cache[x] = (int32_t)(uint32_t)mk[x];
+        for (int x = l; x < n_in; x += WAVE) {
+            L.cache[x] = (int32_t)(uint32_t)mk[x];
+            L.cval[x] = __uint_as_float(mv[x]);
+        }
     // kept own entries, compacted in input order
     int n_own = 0;
     for (int64_t t0 = b; t0 < e; t0 += WAVE) {
@@ -282,7 +295,7 @@ __global__ __launch_bounds__(256) void sym_row_emit(RowsIn rin, const int32_t* _
         L.orank[u] = r;
         const bool both = lb < n_in && (in_lds ? L.cache[lb] : (int32_t)(uint32_t)mk[lb]) == c;
         L.olb[u] = lb;
-        if (both) L.oval[u] += __uint_as_float(pv[m0 + lb]);
+        if (both) L.oval[u] += in_lds ? L.cval[lb] : __uint_as_float(mv[lb]);
         L.scol[r] = c;
         L.mpref[r] = both ? 1 : 0;
     }
@@ -298,7 +311,6 @@ __global__ __launch_bounds__(256) void sym_row_emit(RowsIn rin, const int32_t* _
         carry += __shfl(incl, WAVE - 1, WAVE);
         wave_sync();
     }
-    const int64_t o = row_ptr[i];
     // own entries: (own before) + (mirrored before) - (in both before)
     for (int u = l; u < n_own; u += WAVE) {
         const int32_t c = L.ocol[u];
@@ -317,7 +329,7 @@ __global__ __launch_bounds__(256) void sym_row_emit(RowsIn rin, const int32_t* _
             const int64_t pos = o + x + lb - L.mpref[lb];
             if (pos < cap) {
                 out_col[pos] = c;
-                out_val[pos] = __uint_as_float(pv[m0 + x]) * inv_norm;
+                out_val[pos] = (in_lds ? L.cval[x] : __uint_as_float(mv[x])) * inv_norm;
             }
         }
     }
@@ -347,7 +359,7 @@ static void sym_plan(int64_t N, int64_t nnz_in, SymPlan& p) {
     a.take<int64_t>(N);          // distinct counts per row
     a.take<int64_t>(nb + 1);     // scan block sums / offsets
     a.take<int64_t>(nb + 1);
-    a.take<int32_t>(64);         // error flag
+    a.take<int64_t>(8);          // total and error flag
     p.total = a.used;
 }
 
@@ -369,12 +381,11 @@ static atsne_status sym_run(const SymPlan& p, RowsIn rin, const int32_t* in_col,
     int64_t* cnt = a.take<int64_t>(N);
     int64_t* bsum = a.take<int64_t>(nb + 1);
     int64_t* boff = a.take<int64_t>(nb + 1);
-    int32_t* err = a.take<int32_t>(64);
+    int64_t* fin = a.take<int64_t>(8);  // [0] the total, [1] the error flag (int32 in its low word)
+    int32_t* err = reinterpret_cast<int32_t*>(fin + 1);
     const dim3 rows4((unsigned)ceil_div(N, 4)), blk(256);
     ProfScope ps_("sym_total", st);
-    sym_zero<<<dim3(1), dim3(64), 0, st>>>(err, 64);
-    ATSNE_LAUNCH_CHECK();
-    sym_pack<<<rows4, blk, 0, st>>>(rin, in_col, in_val, N, k0, v0);
+    sym_pack<<<rows4, blk, 0, st>>>(rin, in_col, in_val, N, k0, v0, fin);
     ATSNE_LAUNCH_CHECK();
     ATSNE_TRY(sort_pairs_u64(sort_tmp, p.sort_bytes, k0, v0, k1, v1, E, st, 32, 32 + p.col_bits));
     sym_runs<<<dim3((unsigned)ceil_div(E + 1, 256)), blk, 0, st>>>(k1, E, N, runs);
@@ -385,7 +396,7 @@ static atsne_status sym_run(const SymPlan& p, RowsIn rin, const int32_t* in_col,
     ATSNE_LAUNCH_CHECK();
     sym_scan_small<<<dim3(1), dim3(1024), 0, st>>>(bsum, nb, boff);
     ATSNE_LAUNCH_CHECK();
-    sym_block_scan<<<dim3((unsigned)nb), dim3(1024), 0, st>>>(cnt, N, boff, row_ptr);
+    sym_block_scan<<<dim3((unsigned)nb), dim3(1024), 0, st>>>(cnt, N, boff, row_ptr, fin);
     ATSNE_LAUNCH_CHECK();
     const float inv = (float)(1.0 / (2.0 * (double)N));
     // k <= 128: mirrored runs average k entries, so a 256-entry LDS cache
@@ -401,12 +412,12 @@ static atsne_status sym_run(const SymPlan& p, RowsIn rin, const int32_t* in_col,
         sym_row_emit<SYM_OWN_MAX, 512><<<rows4, blk, 0, st>>>(rin, in_col, in_val, N, k1, v1, runs, row_ptr, inv,
                                                                2 * E, col, val);
     ATSNE_LAUNCH_CHECK();
-    int32_t h_err = 0;
-    ATSNE_HIP(hipMemcpyAsync(nnz_host, row_ptr + N, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    ATSNE_HIP(hipMemcpyAsync(&h_err, err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    int64_t h_fin[2] = {0, 0};
+    ATSNE_HIP(hipMemcpyAsync(h_fin, fin, sizeof(h_fin), hipMemcpyDeviceToHost, st));
     ps_.stop();
     ATSNE_HIP(hipStreamSynchronize(st));
-    ATSNE_REQUIRE(h_err == 0, ATSNE_E_INVALID_ARG, "a conditional row holds more than %d entries", SYM_OWN_MAX);
+    ATSNE_REQUIRE(h_fin[1] == 0, ATSNE_E_INVALID_ARG, "a conditional row holds more than %d entries", SYM_OWN_MAX);
+    *nnz_host = h_fin[0];
     return ATSNE_OK;
 }
 
