@@ -13,9 +13,10 @@
 //   radix_move    stable scatter: each tile, chunk by chunk (4096 keys held
 //                 in registers, 16 per thread), ranks its keys by wave
 //                 multi-split, stages the chunk in LDS in (digit, input)
-//                 order and writes it out so that consecutive lanes store
-//                 consecutive positions of a digit, after the keys of smaller
-//                 digits, of earlier tiles and of earlier keys of the tile
+//                 order, a quarter at a time, and writes it out so that
+//                 consecutive lanes store consecutive positions of a digit,
+//                 after the keys of smaller digits, of earlier tiles and of
+//                 earlier keys of the tile
 // Keys are moved, never compared, so the sort is exact and deterministic.
 #include <algorithm>
 
@@ -28,6 +29,7 @@ constexpr int RADIX_CHUNK = 4096;      // keys per chunk: 256 threads x 16
 constexpr int RADIX_PER_THREAD = 16;
 constexpr int RADIX_MAX_BINS = 1024;   // digits of up to 10 bits
 constexpr int RADIX_MAX_TILES = 4096;  // tiles per sort (a tile is whole chunks)
+constexpr int RADIX_STAGE = 1024;      // slots staged in LDS at a time (a quarter chunk)
 
 struct RadixGeom {
     int64_t n;
@@ -110,8 +112,8 @@ __global__ __launch_bounds__(256) void radix_move(const uint64_t* __restrict__ k
     __shared__ uint32_t wcnt[4][RADIX_MAX_BINS];  // per wave: its count of each digit, then its offset within the digit
     __shared__ uint32_t cofs[RADIX_MAX_BINS];     // per digit: its count in the chunk, then its first staged slot
     __shared__ uint32_t wsum[4];
-    __shared__ uint64_t sk[RADIX_CHUNK];          // the chunk's keys staged in (digit, input) order
-    __shared__ uint32_t sv[RADIX_CHUNK];
+    __shared__ uint64_t sk[RADIX_STAGE];          // a quarter of the chunk staged in (digit, input) order
+    __shared__ uint32_t sv[RADIX_STAGE];
     const int t = threadIdx.x, l = t & 63, w = t >> 6;
     const int bins = 1 << bits;
     for (int b = t; b < bins; b += 256) start[b] = doff[b] + cnt[(int64_t)b * g.n_tiles + blockIdx.x];
@@ -183,31 +185,39 @@ __global__ __launch_bounds__(256) void radix_move(const uint64_t* __restrict__ k
             run += c4[u];
         }
         __syncthreads();
-        // stage the chunk in (digit, input) order: slot = the key's stable
+        // each key's slot in the chunk's (digit, input) order: its stable
         // rank in the chunk, below the chunk's key count
 #pragma unroll
         for (int r = 0; r < RADIX_PER_THREAD; ++r) {
-            if (wb + 64 * r + l < e1) {
-                const uint32_t d = radix_digit(k[r], shift, bits);
-                const uint32_t q = cofs[d] + wcnt[w][d] + pos[r];
-                sk[q] = k[r];
-                if (vin) sv[q] = v[r];
-            }
+            const uint32_t d = radix_digit(k[r], shift, bits);
+            pos[r] = wb + 64 * r + l < e1 ? cofs[d] + wcnt[w][d] + pos[r] : (uint32_t)RADIX_CHUNK;
         }
-        __syncthreads();
-        // write the staged chunk out: consecutive slots of a digit go to
-        // consecutive positions, after the digit's keys of earlier chunks
+        // a quarter of the slots at a time: stage them in LDS, then write
+        // them out so that consecutive slots of a digit go to consecutive
+        // positions, after the digit's keys of earlier chunks
         const int n_c = (int)std::min<int64_t>(RADIX_CHUNK, e1 - c0);
-        for (int q = t; q < n_c; q += 256) {
-            const uint64_t key = sk[q];
-            const uint32_t d = radix_digit(key, shift, bits);
-            const uint32_t p = start[d] + (uint32_t)q - cofs[d];
-            if (p < (uint64_t)g.n) {  // always true: the guard keeps every store in bounds
-                kout[p] = key;
-                if (vout) vout[p] = sv[q];
+        for (int q0 = 0; q0 < n_c; q0 += RADIX_STAGE) {
+#pragma unroll
+            for (int r = 0; r < RADIX_PER_THREAD; ++r) {
+                const uint32_t s = pos[r] - (uint32_t)q0;  // wraps above the quarter when below it
+                if (s < (uint32_t)RADIX_STAGE) {
+                    sk[s] = k[r];
+                    if (vin) sv[s] = v[r];
+                }
             }
+            __syncthreads();
+            const int q1 = std::min(n_c, q0 + RADIX_STAGE);
+            for (int q = q0 + t; q < q1; q += 256) {
+                const uint64_t key = sk[q - q0];
+                const uint32_t d = radix_digit(key, shift, bits);
+                const uint32_t p = start[d] + (uint32_t)q - cofs[d];
+                if (p < (uint64_t)g.n) {  // always true: the guard keeps every store in bounds
+                    kout[p] = key;
+                    if (vout) vout[p] = sv[q - q0];
+                }
+            }
+            __syncthreads();
         }
-        __syncthreads();
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int b = 4 * t + u;
