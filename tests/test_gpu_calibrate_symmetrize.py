@@ -182,6 +182,28 @@ def test_symmetrize_hub_rows(A, ora):
     _check_sym_equal(N, g, o)
 
 
+def test_symmetrize_heavy_tailed_in_degree(A, ora):
+    # neighbour lists drawn with power-law popularity, as kNN graphs of
+    # image-like data have (median in-degree far below k, a few rows listed
+    # by thousands): many mirrored runs exceed the row caches (256 entries
+    # for k <= 128 when emitting, 1024 when counting) and stream through them
+    rng = np.random.default_rng(14)
+    N, k = 8000, 100
+    logw = -0.9 * np.log(np.arange(1, N + 1))[rng.permutation(N)]
+    idx = np.empty((N, k), np.int32)
+    for s in range(0, N, 1000):
+        key = logw[None, :] + rng.gumbel(size=(min(1000, N - s), N))  # Gumbel top-k: sampling without replacement
+        key[np.arange(key.shape[0]), np.arange(s, s + key.shape[0])] = -np.inf  # no self
+        idx[s:s + key.shape[0]] = np.argpartition(-key, k, axis=1)[:, :k]
+    deg = np.bincount(idx.ravel(), minlength=N)
+    assert deg.max() > 1024 and ((deg > 256) & (deg <= 1024)).sum() >= 50
+    P = rng.dirichlet(np.ones(k), size=N)
+    Pf = P.astype(np.float32)
+    g = _sym(A, idx, Pf)
+    o = ora.symmetrize(idx, Pf.astype(np.float64))
+    _check_sym_equal(N, g, o)
+
+
 def test_symmetrize_csr_variable_rows(A, ora):
     rng = np.random.default_rng(13)
     N = 3000
