@@ -225,7 +225,8 @@ __global__ __launch_bounds__(1024) void sym_block_scan(const int64_t* __restrict
 // One wave per row, four rows per workgroup; a row holds at most CAP own
 // entries (its LDS) and its mirrored run (columns and values) is cached in
 // LDS up to RUN entries, so that past the first loads the row's work reads
-// LDS only.
+// LDS only.  Each wave places its row's own entries; the mirrored entries of
+// the four rows are then written by the whole workgroup together.
 template <int CAP, int RUN>
 __global__ __launch_bounds__(256) void sym_row_emit(RowsIn rin, const int32_t* __restrict__ col,
                                                     const float* __restrict__ val, int64_t N,
@@ -243,93 +244,112 @@ __global__ __launch_bounds__(256) void sym_row_emit(RowsIn rin, const int32_t* _
         int32_t cache[RUN];     // the mirrored run's columns
         float cval[RUN];        // and values
     };
+    struct RowInfo {  // a row's extent, for the workgroup's mirrored pass
+        int64_t o, m0;
+        int n_in, n_own, in_lds;
+    };
     __shared__ RowLds lds_all[4];
+    __shared__ RowInfo info[4];
     const int l = lane_id();
     const int w = threadIdx.x >> 6;
     RowLds& L = lds_all[w];
     const int64_t i = (int64_t)blockIdx.x * 4 + w;
-    if (i >= N) return;  // waves are independent: no workgroup barrier below
-    const int64_t b = rin.begin(i), e = rin.end(i);
-    if (e - b > CAP) return;  // refused by the count (error flag)
-    const int64_t o = row_ptr[i];
-    const int64_t m0 = run[i];
-    const int n_in = (int)(run[i + 1] - m0);
-    const uint64_t* mk = key + m0;
-    const uint32_t* mv = pv + m0;
-    const bool in_lds = n_in <= RUN;
-    if (in_lds)
-        for (int x = l; x < n_in; x += WAVE) {
-            L.cache[x] = (int32_t)(uint32_t)mk[x];
-            L.cval[x] = __uint_as_float(mv[x]);
+    // every wave reaches the workgroup barrier below: a row past N, or one
+    // with more than CAP entries (refused by the count's error flag), only
+    // publishes an empty extent
+    const int64_t b = i < N ? rin.begin(i) : 0, e = i < N ? rin.end(i) : 0;
+    if (i < N && e - b <= CAP) {
+        const int64_t o = row_ptr[i];
+        const int64_t m0 = run[i];
+        const int n_in = (int)(run[i + 1] - m0);
+        const uint64_t* mk = key + m0;
+        const uint32_t* mv = pv + m0;
+        const bool in_lds = n_in <= RUN;
+        if (in_lds)
+            for (int x = l; x < n_in; x += WAVE) {
+                L.cache[x] = (int32_t)(uint32_t)mk[x];
+                L.cval[x] = __uint_as_float(mv[x]);
+            }
+        // kept own entries, compacted in input order
+        int n_own = 0;
+        for (int64_t t0 = b; t0 < e; t0 += WAVE) {
+            const int64_t t = t0 + l;
+            const int32_t c = t < e ? col[t] : -1;
+            const bool ok = t < e && sym_valid(c, i, N);
+            const uint64_t m = ballot(ok);
+            if (ok) {
+                const int p = n_own + __popcll(m & lanemask_lt());
+                L.ocol[p] = c;
+                L.oval[p] = val[t];
+            }
+            n_own += __popcll(m);
         }
-    // kept own entries, compacted in input order
-    int n_own = 0;
-    for (int64_t t0 = b; t0 < e; t0 += WAVE) {
-        const int64_t t = t0 + l;
-        const int32_t c = t < e ? col[t] : -1;
-        const bool ok = t < e && sym_valid(c, i, N);
-        const uint64_t m = ballot(ok);
-        if (ok) {
-            const int p = n_own + __popcll(m & lanemask_lt());
-            L.ocol[p] = c;
-            L.oval[p] = val[t];
-        }
-        n_own += __popcll(m);
-    }
-    wave_sync();
-    // per own column: its rank among the own columns, the mirrored entries
-    // before it, and whether it is mirrored too (then its value gains the
-    // mirrored addend, after the own one)
-    // (four columns per LDS read: entries past n_own are padded with INT32_MAX)
-    for (int u = n_own + l; u < ((n_own + 3) & ~3); u += WAVE) L.ocol[u] = INT32_MAX;
-    wave_sync();
-    for (int u = l; u < n_own; u += WAVE) {
-        const int32_t c = L.ocol[u];
-        int r = 0;
-        const int4* oc4 = reinterpret_cast<const int4*>(L.ocol);
-        for (int v = 0; v < (n_own + 3) >> 2; ++v) {
-            const int4 q = oc4[v];
-            r += (q.x < c) + (q.y < c) + (q.z < c) + (q.w < c);
-        }
-        const int lb = in_lds ? lower_lds(L.cache, n_in, c) : lower_src(mk, n_in, c);
-        L.orank[u] = r;
-        const bool both = lb < n_in && (in_lds ? L.cache[lb] : (int32_t)(uint32_t)mk[lb]) == c;
-        L.olb[u] = lb;
-        if (both) L.oval[u] += in_lds ? L.cval[lb] : __uint_as_float(mv[lb]);
-        L.scol[r] = c;
-        L.mpref[r] = both ? 1 : 0;
-    }
-    wave_sync();
-    // mpref: exclusive prefix count of the columns in both, by rank
-    int carry = 0;
-    for (int r0 = 0; r0 <= n_own; r0 += WAVE) {
-        const int r = r0 + l;
-        const int f = r < n_own ? L.mpref[r] : 0;
-        const int incl = (int)wave_incl_scan((uint32_t)f);
         wave_sync();
-        if (r <= n_own) L.mpref[r] = carry + incl - f;
-        carry += __shfl(incl, WAVE - 1, WAVE);
+        // per own column: its rank among the own columns, the mirrored
+        // entries before it, and whether it is mirrored too (then its value
+        // gains the mirrored addend, after the own one)
+        // (four columns per LDS read: entries past n_own are padded with INT32_MAX)
+        for (int u = n_own + l; u < ((n_own + 3) & ~3); u += WAVE) L.ocol[u] = INT32_MAX;
         wave_sync();
-    }
-    // own entries: (own before) + (mirrored before) - (in both before)
-    for (int u = l; u < n_own; u += WAVE) {
-        const int32_t c = L.ocol[u];
-        const int r = L.orank[u];
-        const int64_t pos = o + r + L.olb[u] - L.mpref[r];
-        if (pos < cap) {  // always true: the guard keeps every store in bounds
-            out_col[pos] = c;
-            out_val[pos] = L.oval[u] * inv_norm;
+        for (int u = l; u < n_own; u += WAVE) {
+            const int32_t c = L.ocol[u];
+            int r = 0;
+            const int4* oc4 = reinterpret_cast<const int4*>(L.ocol);
+            for (int v = 0; v < (n_own + 3) >> 2; ++v) {
+                const int4 q = oc4[v];
+                r += (q.x < c) + (q.y < c) + (q.z < c) + (q.w < c);
+            }
+            const int lb = in_lds ? lower_lds(L.cache, n_in, c) : lower_src(mk, n_in, c);
+            L.orank[u] = r;
+            const bool both = lb < n_in && (in_lds ? L.cache[lb] : (int32_t)(uint32_t)mk[lb]) == c;
+            L.olb[u] = lb;
+            if (both) L.oval[u] += in_lds ? L.cval[lb] : __uint_as_float(mv[lb]);
+            L.scol[r] = c;
+            L.mpref[r] = both ? 1 : 0;
         }
-    }
-    // mirrored entries that are not own ones
-    for (int x = l; x < n_in; x += WAVE) {
-        const int32_t c = in_lds ? L.cache[x] : (int32_t)(uint32_t)mk[x];
-        const int lb = lower_lds(L.scol, n_own, c);
-        if (!(lb < n_own && L.scol[lb] == c)) {
-            const int64_t pos = o + x + lb - L.mpref[lb];
-            if (pos < cap) {
+        wave_sync();
+        // mpref: exclusive prefix count of the columns in both, by rank
+        int carry = 0;
+        for (int r0 = 0; r0 <= n_own; r0 += WAVE) {
+            const int r = r0 + l;
+            const int f = r < n_own ? L.mpref[r] : 0;
+            const int incl = (int)wave_incl_scan((uint32_t)f);
+            wave_sync();
+            if (r <= n_own) L.mpref[r] = carry + incl - f;
+            carry += __shfl(incl, WAVE - 1, WAVE);
+            wave_sync();
+        }
+        // own entries: (own before) + (mirrored before) - (in both before)
+        for (int u = l; u < n_own; u += WAVE) {
+            const int32_t c = L.ocol[u];
+            const int r = L.orank[u];
+            const int64_t pos = o + r + L.olb[u] - L.mpref[r];
+            if (pos < cap) {  // always true: the guard keeps every store in bounds
                 out_col[pos] = c;
-                out_val[pos] = (in_lds ? L.cval[x] : __uint_as_float(mv[x])) * inv_norm;
+                out_val[pos] = L.oval[u] * inv_norm;
+            }
+        }
+        if (l == 0) info[w] = RowInfo{o, m0, n_in, n_own, in_lds ? 1 : 0};
+    } else if (l == 0) {
+        info[w] = RowInfo{0, 0, 0, 0, 1};
+    }
+    __syncthreads();
+    // mirrored entries that are not own ones, the four rows' runs taken
+    // together by the whole workgroup, so that a hub row's long run is
+    // shared by 256 lanes: flat index f walks row 0's run, then row 1's, ...
+    const int64_t p1 = info[0].n_in, p2 = p1 + info[1].n_in, p3 = p2 + info[2].n_in, tot = p3 + info[3].n_in;
+    for (int64_t f = threadIdx.x; f < tot; f += 256) {
+        const int r = (f >= p1) + (f >= p2) + (f >= p3);
+        const int x = (int)(f - (r == 0 ? 0 : r == 1 ? p1 : r == 2 ? p2 : p3));
+        const RowInfo& R = info[r];
+        const RowLds& M = lds_all[r];
+        const int32_t c = R.in_lds ? M.cache[x] : (int32_t)(uint32_t)key[R.m0 + x];
+        const int lb = lower_lds(M.scol, R.n_own, c);
+        if (!(lb < R.n_own && M.scol[lb] == c)) {
+            const int64_t pos = R.o + x + lb - M.mpref[lb];
+            if (pos < cap) {  // always true: the guard keeps every store in bounds
+                out_col[pos] = c;
+                out_val[pos] = (R.in_lds ? M.cval[x] : __uint_as_float(pv[R.m0 + x])) * inv_norm;
             }
         }
     }

@@ -182,13 +182,15 @@ def test_symmetrize_hub_rows(A, ora):
     _check_sym_equal(N, g, o)
 
 
-def test_symmetrize_heavy_tailed_in_degree(A, ora):
+@pytest.mark.parametrize("k,form", [(100, "fixed"), (200, "fixed"), (100, "csr")])
+def test_symmetrize_heavy_tailed_in_degree(A, ora, k, form):
     # neighbour lists drawn with power-law popularity, as kNN graphs of
     # image-like data have (median in-degree far below k, a few rows listed
     # by thousands): many mirrored runs exceed the row caches (256 entries
-    # for k <= 128 when emitting, 1024 when counting) and stream through them
+    # for k <= 128, 1024 for k <= 256 and 512 for CSR input when emitting,
+    # 1024 when counting), and a workgroup's rows share their mirrored runs
     rng = np.random.default_rng(14)
-    N, k = 8000, 100
+    N = 8000
     logw = -0.9 * np.log(np.arange(1, N + 1))[rng.permutation(N)]
     idx = np.empty((N, k), np.int32)
     for s in range(0, N, 1000):
@@ -199,7 +201,14 @@ def test_symmetrize_heavy_tailed_in_degree(A, ora):
     assert deg.max() > 1024 and ((deg > 256) & (deg <= 1024)).sum() >= 50
     P = rng.dirichlet(np.ones(k), size=N)
     Pf = P.astype(np.float32)
-    g = _sym(A, idx, Pf)
+    if form == "fixed":
+        g = _sym(A, idx, Pf)
+    else:
+        ptr = np.arange(0, N * k + 1, k, dtype=np.int64)
+        rp, c, v = A.symmetrize_csr(torch.from_numpy(ptr).cuda(), torch.from_numpy(idx.ravel()).cuda(),
+                                    torch.from_numpy(Pf.ravel()).cuda())
+        torch.cuda.synchronize()
+        g = (rp.cpu().numpy(), c.cpu().numpy(), v.cpu().numpy())
     o = ora.symmetrize(idx, Pf.astype(np.float64))
     _check_sym_equal(N, g, o)
 
