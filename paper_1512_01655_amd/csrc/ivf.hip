@@ -639,6 +639,14 @@ atsne_status fp8_seed_thresholds(const float* X, int64_t N, int32_t D, int64_t l
     ATSNE_TRY(atsne_ivf_build(X, N, D, C, init.data(), 0, &ixp, st));
     std::unique_ptr<atsne_ivf, atsne_status (*)(atsne_ivf*)> guard(ixp, atsne_ivf_destroy);
     atsne_ivf& ix = *ixp;
+    const auto tiles = seed_tiles(ix, SEED_PROBE, kc);
+    // decline when the cells are too coarse to pay (e.g. data in one cell):
+    // the lists would cover more than a tenth of all row pairs
+    double pairs = 0;
+    for (int c = 0; c < C; ++c)
+        pairs += (double)(ix.start[c + 1] - ix.start[c]) * (double)tiles[c].size() * IVF_TILE;
+    ATSNE_REQUIRE(pairs <= 0.1 * (double)N * (double)N, ATSNE_E_UNSUPPORTED,
+                  "seeding lists would cover %.0f%% of the row pairs", 100.0 * pairs / ((double)N * (double)N));
     if (order) ATSNE_HIP(hipMemcpyAsync(order, ix.perm, sizeof(int32_t) * N, hipMemcpyDeviceToDevice, st));
     // FP8 copy of the sorted corpus (per-row scales: the rows' FP8 codes,
     // norms and scales equal those of the same rows in the caller's order)
@@ -648,14 +656,6 @@ atsne_status fp8_seed_thresholds(const float* X, int64_t N, int32_t D, int64_t l
     Corpus c8;
     corpus_bind(c8, ATSNE_PREC_FP8_E4M3, ix.Xperm, D, D, cap, cm.p);
     ATSNE_TRY(corpus_prep(c8, 0, cap, N, st));
-    const auto tiles = seed_tiles(ix, SEED_PROBE, kc);
-    // decline when the cells are too coarse to pay (e.g. data in one cell):
-    // the lists would cover more than a tenth of all row pairs
-    double pairs = 0;
-    for (int c = 0; c < C; ++c)
-        pairs += (double)(ix.start[c + 1] - ix.start[c]) * (double)tiles[c].size() * IVF_TILE;
-    ATSNE_REQUIRE(pairs <= 0.1 * (double)N * (double)N, ATSNE_E_UNSUPPORTED,
-                  "seeding lists would cover %.0f%% of the row pairs", 100.0 * pairs / ((double)N * (double)N));
     for (int c0 = 0; c0 < C;) {
         int c1 = c0 + 1;
         while (c1 < C && ix.start[c1 + 1] - ix.start[c0] <= SEED_BATCH_ROWS) ++c1;
