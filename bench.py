@@ -444,12 +444,27 @@ def cpu_baseline(X, mu, k, target_s):
     rows = np.sort(rng.choice(X.shape[0], size=m, replace=False)).astype(np.int32)
     t0 = time.perf_counter()
     idx, d2, nx = o.knn(X, k, query_ids=rows)
+    t1 = time.perf_counter()
     P, _, _, _ = o.calibrate(d2, mu)
     dt = time.perf_counter() - t0
     rec = {"value": m / dt, "unit": "points/s", "cores": cores, "kind": "oracle",
            "sample": "%d of %d query rows: FP64 exact kNN against the full corpus + bisection, %.1f s" % (
-               m, X.shape[0], dt)}
+               m, X.shape[0], dt),
+           "stages_s": {"knn": round(t1 - t0, 3), "calibrate": round(dt - (t1 - t0), 3)},
+           "cpu_model": host_cpu_model()}
     return rec, {"rows": rows, "idx": idx, "d2": d2, "nx": nx, "P": P}
+
+
+def host_cpu_model():
+    """The host CPU's model name (/proc/cpuinfo), or null where unreadable."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def oracle_rows(X, k, mu, rows):
