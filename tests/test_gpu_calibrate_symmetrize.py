@@ -213,6 +213,31 @@ def test_symmetrize_heavy_tailed_in_degree(A, ora, k, form):
     _check_sym_equal(N, g, o)
 
 
+def test_symmetrize_many_entries(A, ora):
+    # 18 M conditional entries: past 4096 x 4096 keys the sort's tiles hold
+    # several 4096-key chunks each (the staged scatter carries each digit's
+    # position from chunk to chunk); the CSR is compared with the oracle's
+    rng = np.random.default_rng(16)
+    N, k = 200000, 90
+    # row i lists (i + 1 + (a_i j + b_i) mod (N - 1)) mod N, j < k: distinct,
+    # never i (a_i coprime to N - 1)
+    a = rng.integers(1, N - 1, size=N)
+    while True:
+        bad = np.gcd(a, N - 1) != 1
+        if not bad.any():
+            break
+        a[bad] = rng.integers(1, N - 1, size=bad.sum())
+    b = rng.integers(0, N - 1, size=N)
+    j = np.arange(k)
+    idx = ((np.arange(N)[:, None] + 1 + (a[:, None] * j[None, :] + b[:, None]) % (N - 1)) % N).astype(np.int32)
+    assert N * k > 4096 * 4096
+    P = rng.dirichlet(np.ones(k), size=N)
+    Pf = P.astype(np.float32)
+    g = _sym(A, idx, Pf)
+    o = ora.symmetrize(idx, Pf.astype(np.float64))
+    _check_sym_equal(N, g, o)
+
+
 def test_symmetrize_csr_variable_rows(A, ora):
     rng = np.random.default_rng(13)
     N = 3000
