@@ -263,6 +263,27 @@ def test_knn_fp8_seeded_equals_unseeded_with_ties(A, monkeypatch):
     assert all(np.array_equal(x, y) for x, y in zip(a, b))
 
 
+def test_knn_fp8_seeding_declines_on_one_cell(A, monkeypatch):
+    # the seeding partition starts from the rows c N / C (C = N / 1000
+    # cells); when they all hold the same point every row joins one cell,
+    # the lists would cover every row pair, and the pass steps aside: the
+    # search runs unseeded, with the unseeded results
+    N = 1 << 18
+    C = N // 1000
+    X = np.random.default_rng(23).normal(size=(N, 32)).astype(np.float32)
+    X[(np.arange(C) * N) // C] = X[0]
+    A.profile_enable(True)
+    try:
+        a = run_knn(A, X, 30, "fp8", 60)
+        assert A.profile_read("seed_total")[1] == 1
+        assert A.profile_read("seed_declined")[1] == 1
+    finally:
+        A.profile_enable(False)
+    monkeypatch.setenv("ATSNE_FP8_SEED", "0")
+    b = run_knn(A, X, 30, "fp8", 60)
+    assert all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
 def test_knn_errors(A):
     import torch
 
