@@ -61,7 +61,6 @@ struct TileGeom {
 constexpr int KNN_XCDS = 8;  // accelerator complex dies; workgroups go round-robin over them
 __host__ __device__ constexpr int qb_of(int) { return 256; }
 constexpr int KT = KNN_KT;      // keys per tile (8 MFMA blocks of 32)
-constexpr int NKB = KT / 32;    // key blocks per tile
 constexpr int CHUNK_UNITS = 8;  // 16-byte units per row per D-chunk (128 bytes)
 
 // LDS tile layout: rows of CHUNK_UNITS unpadded 16-byte units, unit u of row r
